@@ -1,0 +1,220 @@
+"""Throughput of the batched FAST pyramid / NMS / cell-select path on one GPU.
+
+Workload: the uneven 64-frame batch (24 x 752x480, 24 x 1280x720, 16 x 640x480,
+3 pyramid levels each, per-frame t, N and cell), resident in HBM, replayed as one
+graph-captured persistent launch per step.  R distinct resident copies of the
+batch are cycled so consecutive steps do not re-read the same bytes from the
+last-level cache.
+
+One JSON line is printed: whole-job Mpixel/s (level-0 input pixels), plus the
+plain one-frame-per-launch path on the same frames, per-frame latency of the
+plain path, the HBM roofline of the step and the CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(specs) -> int:
+    """Input read once + every pyramid level written once + 8 B per cell."""
+    from paper_2003_13493_amd import fastgrid
+    total = 0
+    for s in specs:
+        dims = fastgrid.fast_pyr_dims(s.width, s.height, s.levels)
+        total += s.width * s.height
+        total += sum(w * h for (w, h, _) in dims[1:])
+        gw, gh = fastgrid.fast_grid_dims(s.width, s.height, s.cell)
+        total += 8 * gw * gh
+    return total
+
+
+def cpu_baseline(specs, frames, budget_s: float) -> dict:
+    import oracle
+    done_px, t_total, nframes = 0, 0.0, 0
+    for s, img in zip(specs, frames):
+        t0 = time.perf_counter()
+        oracle.detect_grid(img, s.width, s.levels, s.t, s.n, s.cell)
+        t_total += time.perf_counter() - t0
+        done_px += s.width * s.height
+        nframes += 1
+        if t_total >= budget_s:
+            break
+    return {"value": round(done_px / t_total / 1e6, 3), "unit": "Mpixel/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {nframes} frames of the 64-frame batch, single-threaded, "
+                      f"{t_total:.1f} s"}
+
+
+def log(msg: str) -> None:
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--instances", type=int, default=8)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--plain-latency-frames", type=int, default=300)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (frames are "
+              "independent, so more GPUs would shard whole frames with no exchange).",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2003_13493_amd import fastgrid, synth
+
+    torch.cuda.set_device(0)
+    log(f"device {torch.cuda.get_device_name(0)}")
+    ctx = fastgrid.Context(0)
+    stream = torch.cuda.current_stream()
+
+    # resident batch instances
+    insts = []
+    frames0 = None
+    for r in range(args.instances):
+        specs = synth.batch64(instance=r)
+        frames = [s.make() for s in specs]
+        if r == 0:
+            frames0 = (specs, frames)
+        pyrs, grids = [], []
+        for s, img in zip(specs, frames):
+            p = fastgrid.Pyramid(s.width, s.height, s.levels)
+            p.upload(img)
+            pyrs.append(p)
+            grids.append(fastgrid.Grid(s.width, s.height, s.cell))
+        jobs = fastgrid.Context.make_jobs(
+            (p, s.t, s.n, s.cell, g) for p, s, g in zip(pyrs, specs, grids))
+        plan = ctx.plan_create(jobs)
+        insts.append((specs, pyrs, grids, jobs, plan))
+    torch.cuda.synchronize()
+    log(f"{len(insts)} resident batch instances ready")
+    specs0 = insts[0][0]
+    px_per_step = sum(s.width * s.height for s in specs0)
+    bytes_per_step = algorithmic_bytes(specs0)
+
+    # ---- batched (graph replay of the persistent launch)
+    for i in range(args.warmup):
+        ctx.plan_launch(insts[i % len(insts)][4], stream)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    t_wall0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(args.steps):
+        ctx.plan_launch(insts[i % len(insts)][4], stream)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+    total_ms = ev[0].elapsed_time(ev[-1])
+    ms_per_step = total_ms / args.steps
+    value = px_per_step * args.steps / (total_ms / 1e3) / 1e6
+
+    log(f"batched: {ms_per_step:.4f} ms/step")
+    # ---- plain path over the same 64 frames: one launch per frame
+    specs, pyrs, grids = insts[0][0], insts[0][1], insts[0][2]
+    for _ in range(3):
+        for s, p, g in zip(specs, pyrs, grids):
+            ctx.detect(p, s.t, s.n, s.cell, g, stream)
+    torch.cuda.synchronize()
+    reps = max(5, args.steps // 10)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        for s, p, g in zip(specs, pyrs, grids):
+            ctx.detect(p, s.t, s.n, s.cell, g, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1) / reps
+    plain_value = px_per_step / (plain_ms / 1e3) / 1e6
+
+    # ---- plain per-frame latency (sync after each frame), 752x480 L=3 frame
+    lspec = synth.PLAIN_752
+    limg = lspec.make()
+    lp = fastgrid.Pyramid(lspec.width, lspec.height, lspec.levels)
+    lp.upload(limg)
+    lg = fastgrid.Grid(lspec.width, lspec.height, lspec.cell)
+    lat = []
+    for i in range(args.plain_latency_frames + 20):
+        t0 = time.perf_counter()
+        ctx.detect(lp, lspec.t, lspec.n, lspec.cell, lg, stream)
+        stream.synchronize()
+        if i >= 20:
+            lat.append((time.perf_counter() - t0) * 1e3)
+    lat = np.array(lat)
+
+    achieved = bytes_per_step / (ms_per_step / 1e3) / 1e9
+    out = {
+        "metric": "Mpixel/s detect+NMS+cell-select (batched vs plain, bit-exact); "
+                  "p50/p99 frame latency",
+        "value": round(value, 1),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": "batch64: 24x752x480 + 24x1280x720 + 16x640x480, 3 levels, per-frame "
+                        "t in {8,10,15,20}, N in {9,10,12}, cell in {16,32,64}; one "
+                        "graph-captured persistent launch per step",
+            "frames_per_step": len(specs0),
+            "level0_pixels_per_step": px_per_step,
+            "resident_instances": args.instances,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "algorithmic_bytes_per_launch": bytes_per_step,
+        },
+        "step_ms_p50": round(float(np.percentile(step_ms, 50)), 5),
+        "step_ms_p99": round(float(np.percentile(step_ms, 99)), 5),
+        "plain": {
+            "value": round(plain_value, 1),
+            "unit": "Mpixel/s",
+            "ms_per_64_frames": round(plain_ms, 4),
+            "batched_speedup": round(value / plain_value, 3),
+        },
+        "latency_ms": {
+            "workload": "plain path, one 752x480 L=3 frame, host sync after each",
+            "p50": round(float(np.percentile(lat, 50)), 4),
+            "p99": round(float(np.percentile(lat, 99)), 4),
+        },
+        "wall_s_timed": round(t_wall, 3),
+    }
+    log(f"plain: {plain_ms:.4f} ms per 64 frames; latency p50 {np.percentile(lat, 50):.4f} ms")
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(frames0[0], frames0[1], args.cpu_budget)
+        out["cpu_baseline"]["sample"] += f"; host: {os.cpu_count()} logical CPUs"
+    for inst in insts:
+        ctx.plan_destroy(inst[4])
+    ctx.close()
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,178 @@
+/*
+ * fastgrid.h — C ABI of libfastgrid.so: FAST corner detection on an image
+ * pyramid with 3x3 non-maxima suppression and one feature per grid cell,
+ * on an AMD Instinct MI355X (gfx950).
+ *
+ * The operation follows "Faster than FAST: GPU-Accelerated Frontend for
+ * High-Speed VIO" (Nagy, Foehn, Scaramuzza, IROS 2020):
+ *   - image pyramid, each level half the previous one (Section II-B, and the
+ *     stage list of Section III-C);
+ *   - FAST segment test on the 16-pixel radius-3 Bresenham circle with
+ *     threshold t (the paper's epsilon) and arc length N (Section II-D, Eq. (1));
+ *     corner score 0 when the test fails (Section II-D);
+ *   - non-maxima suppression in the 3x3 Moore neighbourhood (Section I-B, n=1);
+ *   - one feature per grid cell, the highest score, over all levels on one
+ *     shared level-0 grid (Section II-B, Section II-C, Algorithm 1).
+ *
+ * Exact definitions used where the paper leaves a choice:
+ *   - level k+1 pixel = (a+b+c+d+2)>>2 of the 2x2 block of level k; level sizes
+ *     are floor halvings (W_k = W_{k-1}/2, H_k = H_{k-1}/2);
+ *   - a pixel is tested only if 3 <= x <= W_k-4 and 3 <= y <= H_k-4;
+ *   - brighter: p > c + t; darker: p < c - t; corner iff a circular run of at
+ *     least N brighter, or of at least N darker, circle pixels exists;
+ *   - score = max(sum over brighter circle pixels of (p-c-t),
+ *                 sum over darker circle pixels of (c-p-t)), in [N, 4080];
+ *   - NMS keeps a pixel iff its score is > 0 and it ranks above all 8
+ *     neighbours by (score descending, row-major index ascending);
+ *   - the cell of a level-k survivor (x, y) is ((x<<k)/cell, (y<<k)/cell); the
+ *     cell keeps its survivor of highest score, then lowest level, then lowest
+ *     row-major index at that level.
+ *
+ * Conventions
+ *   - Every call returns int: FAST_OK (0) or a negative FAST_E* code.
+ *   - Argument validation is synchronous: on FAST_EINVAL nothing is enqueued.
+ *   - Work is enqueued asynchronously on the given stream (a hipStream_t passed
+ *     as void*, NULL for the null stream); results are valid after the stream
+ *     synchronises or fast_poll reports completion.  Device faults surface as
+ *     FAST_EHIP from a later call.
+ *   - All image planes and output arrays are device memory owned by the
+ *     caller; the library never frees them.  The library owns only its context
+ *     (job tables, queue counters, events, graphs, scratch).
+ *   - One host thread at a time per context.
+ */
+#ifndef FASTGRID_H
+#define FASTGRID_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FAST_OK = 0,
+    FAST_EINVAL = -1,     /* invalid argument; nothing was enqueued */
+    FAST_ENOMEM = -2,     /* a library-owned allocation failed */
+    FAST_EHIP = -3,       /* a HIP runtime call failed (detail: fast_last_error) */
+    FAST_EBUSY = -4,      /* all in-flight slots are taken */
+    FAST_ETIMEDOUT = -5   /* fast_wait ran out of time */
+};
+
+#define FAST_MAX_LEVELS 8
+#define FAST_MAX_CELL 256
+#define FAST_MAX_JOBS 4096
+
+typedef struct fast_ctx fast_ctx;          /* opaque, library-owned */
+
+/* One uint8 grayscale plane in device memory: row y starts at data + y*pitch.
+ * Requirements: width >= 1, height >= 1, width <= 65535, height <= 65535,
+ * pitch >= width, pitch % 16 == 0, (uintptr_t)data % 16 == 0.
+ * Bytes between width and pitch are never read as pixels and never written. */
+typedef struct {
+    uint8_t *data;
+    int32_t width;
+    int32_t height;
+    int32_t pitch;
+} fast_plane;
+
+/* One grid-cell result (8 bytes).  x, y are coordinates on pyramid level
+ * `level`; the level-0 position is (x << level, y << level).  An empty cell is
+ * x = y = 0xFFFF, score = 0, level = 0xFF, reserved = 0. */
+typedef struct {
+    uint16_t x;
+    uint16_t y;
+    uint16_t score;
+    uint8_t level;
+    uint8_t reserved;
+} fast_feature;
+
+/* One detection request for the batched entry point. */
+typedef struct {
+    const fast_plane *pyr;   /* host array of `levels` planes: [0] input, [1..] written */
+    int32_t levels;          /* 1..FAST_MAX_LEVELS */
+    int32_t t;               /* threshold, 0..255 */
+    int32_t n;               /* arc length N, 1..16 */
+    int32_t cell;            /* cell side in level-0 pixels, multiple of 2^(levels-1), <= 256 */
+    fast_feature *out;       /* device array of gw*gh slots, row-major */
+} fast_job;
+
+/* Create a context on HIP device `hip_device`.  *out receives the context.
+ * Errors: FAST_EINVAL (null out, bad device), FAST_EHIP, FAST_ENOMEM. */
+int fast_ctx_create(int hip_device, fast_ctx **out);
+
+/* Destroy a context after synchronising its outstanding work.  NULL is a no-op. */
+void fast_ctx_destroy(fast_ctx *ctx);
+
+/* Static description of a status code. */
+const char *fast_strerror(int status);
+
+/* Detail of the last error on this context (e.g. the hipError_t name); the
+ * string stays valid until the next call on the context. */
+const char *fast_last_error(const fast_ctx *ctx);
+
+/* Level sizes of a pyramid: fills dims[0..levels-1] with data = NULL,
+ * width/height the floor halvings, pitch = width rounded up to 64.
+ * Errors: FAST_EINVAL (bad sizes, levels out of range, a level of size 0). */
+int fast_pyr_dims(int width, int height, int levels, fast_plane *dims);
+
+/* Grid size for a cell: *gw = ceil(width/cell), *gh = ceil(height/cell). */
+int fast_grid_dims(int width, int height, int cell, int *gw, int *gh);
+
+/* Build pyramid levels 1..levels-1 of pyr (a host array of device planes) from
+ * level 0 (Section II-B).  Enqueued on `stream`.
+ * Errors: FAST_EINVAL (see fast_plane; level sizes must be floor halvings). */
+int fast_pyr_build(fast_ctx *ctx, const fast_plane *pyr, int levels, void *stream);
+
+/* Plain path, one frame: build levels 1..levels-1 into pyr[1..] and write one
+ * fast_feature per grid cell into `out` (device, gw*gh slots, row-major).
+ * Everything is enqueued on `stream`; no host synchronisation.
+ * Errors: FAST_EINVAL for null pointers, levels not in 1..8, t not in 0..255,
+ * n not in 1..16, cell < 1 or cell > 256 or cell % 2^(levels-1) != 0, a plane
+ * that breaks the fast_plane rules, level sizes other than floor halvings;
+ * FAST_EHIP if a launch fails. */
+int fast_detect_grid(fast_ctx *ctx, const fast_plane *pyr, int levels, int t, int n,
+                     int cell, fast_feature *out, void *stream);
+
+/* Batched path: all `njobs` requests (1..FAST_MAX_JOBS, any mix of sizes and
+ * parameters) run in one persistent launch fed by a device-side work queue.
+ * The job table is copied to the device before return-free enqueue on
+ * `stream`; *ticket identifies the submission for fast_poll / fast_wait.
+ * Each job is validated like fast_detect_grid; one bad job rejects the whole
+ * submission with FAST_EINVAL and nothing is enqueued.  FAST_EBUSY if the
+ * context's in-flight table slots are all taken by unfinished submissions. */
+int fast_submit(fast_ctx *ctx, const fast_job *jobs, int njobs, void *stream,
+                uint64_t *ticket);
+
+/* 1 if the submission has finished, 0 if still pending; never blocks.
+ * Errors: FAST_EINVAL for an unknown ticket, FAST_EHIP for a device error. */
+int fast_poll(fast_ctx *ctx, uint64_t ticket);
+
+/* Block until the submission finishes or timeout_ms passes (timeout_ms < 0:
+ * no limit).  Returns FAST_OK, FAST_ETIMEDOUT, or an error. */
+int fast_wait(fast_ctx *ctx, uint64_t ticket, int timeout_ms);
+
+/* A resident batch: the job table is uploaded once into context-owned device
+ * memory and the launch sequence is captured into a HIP graph; each replay
+ * re-runs the whole batch on the frames currently in the jobs' planes.
+ * *plan_id receives a handle (>= 0).  Errors as for fast_submit, FAST_ENOMEM. */
+int fast_plan_create(fast_ctx *ctx, const fast_job *jobs, int njobs, int *plan_id);
+
+/* Replay a resident batch on `stream`; *ticket as for fast_submit. */
+int fast_plan_launch(fast_ctx *ctx, int plan_id, void *stream, uint64_t *ticket);
+
+/* Release a resident batch (after its launches complete). */
+int fast_plan_destroy(fast_ctx *ctx, int plan_id);
+
+/* Launch-shape tuning (the autotuner's knobs), per context.
+ * region: side of the square region one workgroup owns, in level-0 pixels,
+ *         rounded up to a multiple of the cell (16..256);
+ * block:  threads per workgroup (64, 128, 256, 512 or 1024);
+ * persistent_blocks_per_cu: workgroups per compute unit for the persistent
+ *         batched kernel (1..16).
+ * Errors: FAST_EINVAL for values out of range. */
+int fast_set_launch(fast_ctx *ctx, int region, int block, int persistent_blocks_per_cu);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

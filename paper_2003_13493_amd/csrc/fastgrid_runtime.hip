@@ -1,0 +1,446 @@
+// Host runtime of libfastgrid: argument validation, contexts, the plain
+// entry point, batched submission with tickets, and graph-captured resident
+// batches.  See include/fastgrid.h for the contract of every entry point.
+#include <string.h>
+
+#include <chrono>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "fg_internal.h"
+
+#define FG_API extern "C" __attribute__((visibility("default")))
+
+static_assert(sizeof(fast_plane) == 24, "fast_plane layout is part of the ABI");
+static_assert(sizeof(fast_feature) == 8, "fast_feature layout is part of the ABI");
+static_assert(sizeof(fast_job) == 32, "fast_job layout is part of the ABI");
+
+namespace {
+
+constexpr int TICKET_RING = 256;   // submissions tracked per context
+constexpr int TABLE_SLOTS = 8;     // job tables that may be in flight at once
+
+struct TableSlot {
+    fg_job *host = nullptr;        // pinned staging copy
+    fg_job *dev = nullptr;
+    unsigned *counter = nullptr;   // persistent-queue counters (2 words)
+    uint64_t ticket = 0;           // last submission that used this slot
+};
+
+struct Plan {
+    bool live = false;
+    fg_job *dev = nullptr;
+    unsigned *counter = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int njobs = 0;
+};
+
+}  // namespace
+
+struct fast_ctx {
+    int device = 0;
+    fg_launch launch{};
+    std::string err;
+    uint64_t next_ticket = 1;
+    hipEvent_t events[TICKET_RING] = {};
+    uint64_t event_ticket[TICKET_RING] = {};
+    TableSlot slots[TABLE_SLOTS];
+    std::vector<Plan> plans;
+    hipStream_t capture_stream = nullptr;
+};
+
+namespace {
+
+int fail(fast_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+int hip_fail(fast_ctx *c, hipError_t e, const char *what) {
+    if (c) c->err = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+    return FAST_EHIP;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+bool plane_ok(const fast_plane &p, std::string &why) {
+    if (!p.data) { why = "plane data is NULL"; return false; }
+    if (((uintptr_t)p.data & 15u) != 0) { why = "plane data not 16-byte aligned"; return false; }
+    if (p.width < 1 || p.height < 1) { why = "plane has zero size"; return false; }
+    if (p.width > 65535 || p.height > 65535) { why = "plane larger than 65535"; return false; }
+    if (p.pitch < p.width) { why = "pitch < width"; return false; }
+    if (p.pitch % 16 != 0) { why = "pitch not a multiple of 16"; return false; }
+    return true;
+}
+
+int check_pyr(fast_ctx *c, const fast_plane *pyr, int levels) {
+    if (!pyr) return fail(c, FAST_EINVAL, "pyr is NULL");
+    if (levels < 1 || levels > FAST_MAX_LEVELS) return fail(c, FAST_EINVAL, "levels not in 1..8");
+    std::string why;
+    for (int k = 0; k < levels; ++k) {
+        if (!plane_ok(pyr[k], why)) return fail(c, FAST_EINVAL, "level " + std::to_string(k) + ": " + why);
+        if (k > 0 && (pyr[k].width != pyr[k - 1].width / 2 || pyr[k].height != pyr[k - 1].height / 2))
+            return fail(c, FAST_EINVAL, "level " + std::to_string(k) + " is not the floor half of level " +
+                                            std::to_string(k - 1));
+    }
+    return FAST_OK;
+}
+
+int check_params(fast_ctx *c, int levels, int t, int n, int cell) {
+    if (t < 0 || t > 255) return fail(c, FAST_EINVAL, "t not in 0..255");
+    if (n < 1 || n > 16) return fail(c, FAST_EINVAL, "n not in 1..16");
+    if (cell < 1 || cell > FAST_MAX_CELL) return fail(c, FAST_EINVAL, "cell not in 1..256");
+    if (cell % (1 << (levels - 1)) != 0) return fail(c, FAST_EINVAL, "cell not a multiple of 2^(levels-1)");
+    return FAST_OK;
+}
+
+int make_job(fast_ctx *c, const fast_plane *pyr, int levels, int t, int n, int cell, fast_feature *out,
+             fg_job &j) {
+    int rc = check_pyr(c, pyr, levels);
+    if (rc) return rc;
+    rc = check_params(c, levels, t, n, cell);
+    if (rc) return rc;
+    if (!out) return fail(c, FAST_EINVAL, "out is NULL");
+    memset(&j, 0, sizeof(j));
+    for (int k = 0; k < levels; ++k) {
+        j.lvl[k] = pyr[k].data;
+        j.w[k] = pyr[k].width;
+        j.h[k] = pyr[k].height;
+        j.pitch[k] = pyr[k].pitch;
+    }
+    j.levels = levels;
+    j.t = t;
+    j.n = n;
+    j.cell = cell;
+    j.out = out;
+    fg_job_layout(j, c->launch);
+    return FAST_OK;
+}
+
+// Record the completion event of a new submission; returns its ticket.
+int record_ticket(fast_ctx *c, hipStream_t s, uint64_t *ticket) {
+    const uint64_t tk = c->next_ticket;
+    const int i = (int)(tk % TICKET_RING);
+    if (c->event_ticket[i] != 0) {
+        // recycle: the previous holder of this event must be finished
+        hipError_t e = hipEventSynchronize(c->events[i]);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize");
+    }
+    hipError_t e = hipEventRecord(c->events[i], s);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventRecord");
+    c->event_ticket[i] = tk;
+    c->next_ticket = tk + 1;
+    if (ticket) *ticket = tk;
+    return FAST_OK;
+}
+
+// 1 done, 0 pending, <0 error.
+int ticket_state(fast_ctx *c, uint64_t tk) {
+    if (tk == 0 || tk >= c->next_ticket) return fail(c, FAST_EINVAL, "unknown ticket");
+    if (c->event_ticket[tk % TICKET_RING] != tk)
+        return 1;   // its event was recycled, which only happens after it completed
+    hipError_t e = hipEventQuery(c->events[tk % TICKET_RING]);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    return hip_fail(c, e, "hipEventQuery");
+}
+
+int build_table(fast_ctx *c, const fast_job *jobs, int njobs, fg_job *table, int &total, int &max_levels,
+                int &max_w1, int &max_h1) {
+    if (!jobs) return fail(c, FAST_EINVAL, "jobs is NULL");
+    if (njobs < 1 || njobs > FAST_MAX_JOBS) return fail(c, FAST_EINVAL, "njobs not in 1..4096");
+    total = 0;
+    max_levels = 1;
+    max_w1 = 1;
+    max_h1 = 1;
+    for (int i = 0; i < njobs; ++i) {
+        const fast_job &q = jobs[i];
+        int rc = make_job(c, q.pyr, q.levels, q.t, q.n, q.cell, q.out, table[i]);
+        if (rc) {
+            c->err = "job " + std::to_string(i) + ": " + c->err;
+            return rc;
+        }
+        table[i].region_base = total;
+        total += table[i].rx * table[i].ry;
+        if (q.levels > max_levels) max_levels = q.levels;
+        if (q.levels > 1) {
+            if (table[i].w[1] > max_w1) max_w1 = table[i].w[1];
+            if (table[i].h[1] > max_h1) max_h1 = table[i].h[1];
+        }
+    }
+    return FAST_OK;
+}
+
+}  // namespace
+
+FG_API const char *fast_strerror(int status) {
+    switch (status) {
+        case FAST_OK: return "success";
+        case FAST_EINVAL: return "invalid argument";
+        case FAST_ENOMEM: return "out of memory";
+        case FAST_EHIP: return "HIP runtime error";
+        case FAST_EBUSY: return "all in-flight slots busy";
+        case FAST_ETIMEDOUT: return "timed out";
+        default: return "unknown status";
+    }
+}
+
+FG_API const char *fast_last_error(const fast_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+FG_API int fast_ctx_create(int hip_device, fast_ctx **out) {
+    if (!out) return FAST_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) return FAST_EINVAL;
+    fast_ctx *c = new (std::nothrow) fast_ctx();
+    if (!c) return FAST_ENOMEM;
+    c->device = hip_device;
+    DeviceGuard g(hip_device);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) != hipSuccess || cus < 1)
+        cus = 256;
+    c->launch.num_cu = cus;
+    c->launch.region = 64;
+    c->launch.block = 256;
+    c->launch.blocks_per_cu = 4;
+    for (int i = 0; i < TICKET_RING; ++i) {
+        hipError_t e = hipEventCreateWithFlags(&c->events[i], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            fast_ctx_destroy(c);
+            return FAST_EHIP;
+        }
+    }
+    *out = c;
+    return FAST_OK;
+}
+
+FG_API void fast_ctx_destroy(fast_ctx *c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto &p : c->plans) {
+        if (p.exec) (void)hipGraphExecDestroy(p.exec);
+        if (p.graph) (void)hipGraphDestroy(p.graph);
+        if (p.dev) (void)hipFree(p.dev);
+        if (p.counter) (void)hipFree(p.counter);
+    }
+    for (auto &s : c->slots) {
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+        if (s.counter) (void)hipFree(s.counter);
+    }
+    for (auto &e : c->events)
+        if (e) (void)hipEventDestroy(e);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    delete c;
+}
+
+FG_API int fast_pyr_dims(int width, int height, int levels, fast_plane *dims) {
+    if (!dims || levels < 1 || levels > FAST_MAX_LEVELS || width < 1 || height < 1 || width > 65535 ||
+        height > 65535)
+        return FAST_EINVAL;
+    int w = width, h = height;
+    for (int k = 0; k < levels; ++k) {
+        if (w < 1 || h < 1) return FAST_EINVAL;
+        dims[k].data = nullptr;
+        dims[k].width = w;
+        dims[k].height = h;
+        dims[k].pitch = (w + 63) / 64 * 64;
+        w /= 2;
+        h /= 2;
+    }
+    return FAST_OK;
+}
+
+FG_API int fast_grid_dims(int width, int height, int cell, int *gw, int *gh) {
+    if (!gw || !gh || width < 1 || height < 1 || cell < 1) return FAST_EINVAL;
+    *gw = (width + cell - 1) / cell;
+    *gh = (height + cell - 1) / cell;
+    return FAST_OK;
+}
+
+FG_API int fast_set_launch(fast_ctx *c, int region, int block, int bpc) {
+    if (!c) return FAST_EINVAL;
+    if (region < 16 || region > 256) return fail(c, FAST_EINVAL, "region not in 16..256");
+    if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
+        return fail(c, FAST_EINVAL, "block not one of 64,128,256,512,1024");
+    if (bpc < 1 || bpc > 16) return fail(c, FAST_EINVAL, "blocks per CU not in 1..16");
+    c->launch.region = region;
+    c->launch.block = block;
+    c->launch.blocks_per_cu = bpc;
+    return FAST_OK;
+}
+
+FG_API int fast_pyr_build(fast_ctx *c, const fast_plane *pyr, int levels, void *stream) {
+    if (!c) return FAST_EINVAL;
+    int rc = check_pyr(c, pyr, levels);
+    if (rc) return rc;
+    fg_job j;
+    memset(&j, 0, sizeof(j));
+    for (int k = 0; k < levels; ++k) {
+        j.lvl[k] = pyr[k].data;
+        j.w[k] = pyr[k].width;
+        j.h[k] = pyr[k].height;
+        j.pitch[k] = pyr[k].pitch;
+    }
+    j.levels = levels;
+    DeviceGuard g(c->device);
+    hipError_t e = fg_launch_pyramid(j, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pyramid launch");
+    return FAST_OK;
+}
+
+FG_API int fast_detect_grid(fast_ctx *c, const fast_plane *pyr, int levels, int t, int n, int cell,
+                            fast_feature *out, void *stream) {
+    if (!c) return FAST_EINVAL;
+    fg_job j;
+    int rc = make_job(c, pyr, levels, t, n, cell, out, j);
+    if (rc) return rc;
+    DeviceGuard g(c->device);
+    hipError_t e = fg_launch_plain(j, c->launch, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "detect launch");
+    return FAST_OK;
+}
+
+FG_API int fast_submit(fast_ctx *c, const fast_job *jobs, int njobs, void *stream, uint64_t *ticket) {
+    if (!c) return FAST_EINVAL;
+    if (!ticket) return fail(c, FAST_EINVAL, "ticket is NULL");
+    // pick a table slot whose last submission has finished
+    int slot = -1;
+    for (int i = 0; i < TABLE_SLOTS && slot < 0; ++i) {
+        const uint64_t tk = c->slots[i].ticket;
+        if (tk == 0) slot = i;
+        else {
+            int st = ticket_state(c, tk);
+            if (st < 0) return st;
+            if (st == 1) slot = i;
+        }
+    }
+    if (slot < 0) return fail(c, FAST_EBUSY, "all job tables are in flight");
+    DeviceGuard g(c->device);
+    TableSlot &S = c->slots[slot];
+    if (!S.host) {
+        hipError_t e = hipHostMalloc((void **)&S.host, sizeof(fg_job) * FAST_MAX_JOBS, hipHostMallocDefault);
+        if (e != hipSuccess) { S.host = nullptr; return hip_fail(c, e, "hipHostMalloc job table"); }
+        e = hipMalloc((void **)&S.dev, sizeof(fg_job) * FAST_MAX_JOBS);
+        if (e != hipSuccess) { S.dev = nullptr; return hip_fail(c, e, "hipMalloc job table"); }
+        e = hipMalloc((void **)&S.counter, 2 * sizeof(unsigned));
+        if (e != hipSuccess) { S.counter = nullptr; return hip_fail(c, e, "hipMalloc counter"); }
+        e = hipMemset(S.counter, 0, 2 * sizeof(unsigned));
+        if (e != hipSuccess) return hip_fail(c, e, "hipMemset counter");
+    }
+    int total, max_levels, mw1, mh1;
+    int rc = build_table(c, jobs, njobs, S.host, total, max_levels, mw1, mh1);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(S.dev, S.host, sizeof(fg_job) * njobs, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(c, e, "job table upload");
+    e = fg_launch_batch(S.dev, njobs, total, max_levels, mw1, mh1, S.counter, c->launch, s);
+    if (e != hipSuccess) return hip_fail(c, e, "batch launch");
+    rc = record_ticket(c, s, ticket);
+    if (rc) return rc;
+    S.ticket = *ticket;
+    return FAST_OK;
+}
+
+FG_API int fast_poll(fast_ctx *c, uint64_t ticket) {
+    if (!c) return FAST_EINVAL;
+    DeviceGuard g(c->device);
+    return ticket_state(c, ticket);
+}
+
+FG_API int fast_wait(fast_ctx *c, uint64_t ticket, int timeout_ms) {
+    if (!c) return FAST_EINVAL;
+    DeviceGuard g(c->device);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        int st = ticket_state(c, ticket);
+        if (st < 0) return st;
+        if (st == 1) return FAST_OK;
+        if (timeout_ms >= 0) {
+            auto ms = std::chrono::duration_cast<std::chrono::milliseconds>(std::chrono::steady_clock::now() - t0);
+            if (ms.count() >= timeout_ms) return fail(c, FAST_ETIMEDOUT, "wait timed out");
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+FG_API int fast_plan_create(fast_ctx *c, const fast_job *jobs, int njobs, int *plan_id) {
+    if (!c) return FAST_EINVAL;
+    if (!plan_id) return fail(c, FAST_EINVAL, "plan_id is NULL");
+    std::vector<fg_job> table((size_t)(njobs > 0 ? njobs : 1));
+    int total, max_levels, mw1, mh1;
+    int rc = build_table(c, jobs, njobs, table.data(), total, max_levels, mw1, mh1);
+    if (rc) return rc;
+    DeviceGuard g(c->device);
+    Plan p;
+    p.njobs = njobs;
+    hipError_t e = hipMalloc((void **)&p.dev, sizeof(fg_job) * njobs);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMalloc plan table");
+    e = hipMalloc((void **)&p.counter, 2 * sizeof(unsigned));
+    if (e != hipSuccess) { (void)hipFree(p.dev); return hip_fail(c, e, "hipMalloc plan counter"); }
+    e = hipMemcpy(p.dev, table.data(), sizeof(fg_job) * njobs, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p.counter, 0, 2 * sizeof(unsigned));
+    if (e == hipSuccess && !c->capture_stream) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = fg_launch_batch(p.dev, njobs, total, max_levels, mw1, mh1, p.counter, c->launch,
+                                        c->capture_stream);
+        e = hipStreamEndCapture(c->capture_stream, &p.graph);
+        if (le != hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p.exec, p.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (p.graph) (void)hipGraphDestroy(p.graph);
+        (void)hipFree(p.dev);
+        (void)hipFree(p.counter);
+        return hip_fail(c, e, "plan capture");
+    }
+    p.live = true;
+    c->plans.push_back(p);
+    *plan_id = (int)c->plans.size() - 1;
+    return FAST_OK;
+}
+
+FG_API int fast_plan_launch(fast_ctx *c, int plan_id, void *stream, uint64_t *ticket) {
+    if (!c) return FAST_EINVAL;
+    if (plan_id < 0 || plan_id >= (int)c->plans.size() || !c->plans[plan_id].live)
+        return fail(c, FAST_EINVAL, "unknown plan");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipGraphLaunch(c->plans[plan_id].exec, s);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
+    uint64_t tk;
+    int rc = record_ticket(c, s, &tk);
+    if (rc) return rc;
+    if (ticket) *ticket = tk;
+    return FAST_OK;
+}
+
+FG_API int fast_plan_destroy(fast_ctx *c, int plan_id) {
+    if (!c) return FAST_EINVAL;
+    if (plan_id < 0 || plan_id >= (int)c->plans.size() || !c->plans[plan_id].live)
+        return fail(c, FAST_EINVAL, "unknown plan");
+    DeviceGuard g(c->device);
+    Plan &p = c->plans[plan_id];
+    (void)hipDeviceSynchronize();
+    if (p.exec) (void)hipGraphExecDestroy(p.exec);
+    if (p.graph) (void)hipGraphDestroy(p.graph);
+    (void)hipFree(p.dev);
+    (void)hipFree(p.counter);
+    p = Plan();
+    return FAST_OK;
+}

@@ -1,0 +1,46 @@
+// Internal declarations shared by the kernels and the host runtime of
+// libfastgrid.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fastgrid.h"
+
+// Device-side description of one detection job (one frame).
+struct fg_job {
+    uint8_t *lvl[FAST_MAX_LEVELS];   // level planes; [0] is the input
+    int32_t w[FAST_MAX_LEVELS];
+    int32_t h[FAST_MAX_LEVELS];
+    int32_t pitch[FAST_MAX_LEVELS];
+    int32_t levels, t, n, cell;
+    fast_feature *out;               // gw*gh slots
+    int32_t gw, gh;                  // grid size in cells
+    int32_t rcells;                  // cells per region side
+    int32_t rx, ry;                  // regions across, down
+    int32_t region_base;             // first work item of this job in a batch
+};
+
+// Launch shape knobs (set per context by fast_set_launch / the autotuner).
+struct fg_launch {
+    int region;          // target region side in level-0 pixels
+    int block;           // threads per workgroup
+    int blocks_per_cu;   // persistent kernel occupancy target
+    int num_cu;          // compute units on the device
+};
+
+// Fill the derived fields of a job (grid, regions) for a launch shape.
+void fg_job_layout(fg_job &j, const fg_launch &L);
+
+// Plain path: one frame.  Enqueues the pyramid (levels 1..L-1) and detection.
+hipError_t fg_launch_plain(const fg_job &j, const fg_launch &L, hipStream_t s);
+
+// Pyramid only, one frame.
+hipError_t fg_launch_pyramid(const fg_job &j, hipStream_t s);
+
+// Batched path: `jobs_dev` is a device copy of njobs jobs whose region_base
+// fields are prefix sums; `total` is the number of work items; `counter` holds
+// two zero-initialised uint32 words that the kernel resets itself on exit.
+hipError_t fg_launch_batch(const fg_job *jobs_dev, int njobs, int total, int max_levels,
+                           int max_w1, int max_h1, unsigned *counter, const fg_launch &L,
+                           hipStream_t s);

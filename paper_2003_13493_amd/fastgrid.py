@@ -1,0 +1,281 @@
+"""ctypes binding of ``libfastgrid.so`` (see include/fastgrid.h).
+
+Argument marshalling only: every step of the detector runs in the library's
+HIP kernels.  The functions keep the C names; device memory and streams come
+from PyTorch (``uint8`` CUDA tensors of shape (height, pitch) for planes, and
+``torch.cuda.Stream`` / the current stream for ordering).
+
+There is no fallback: if the library is missing or no GPU is present, the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfastgrid.so")
+
+FAST_OK, FAST_EINVAL, FAST_ENOMEM, FAST_EHIP, FAST_EBUSY, FAST_ETIMEDOUT = 0, -1, -2, -3, -4, -5
+FAST_MAX_LEVELS = 8
+
+FEATURE_DTYPE = np.dtype([("x", "<u2"), ("y", "<u2"), ("score", "<u2"),
+                          ("level", "u1"), ("reserved", "u1")])
+EMPTY = (0xFFFF, 0xFFFF, 0, 0xFF)
+
+EXPORTS = ("fast_ctx_create", "fast_ctx_destroy", "fast_strerror", "fast_last_error",
+           "fast_pyr_dims", "fast_grid_dims", "fast_pyr_build", "fast_detect_grid",
+           "fast_submit", "fast_poll", "fast_wait", "fast_plan_create", "fast_plan_launch",
+           "fast_plan_destroy", "fast_set_launch")
+
+
+class fast_plane(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("pitch", ctypes.c_int32)]
+
+
+class fast_job(ctypes.Structure):
+    _fields_ = [("pyr", ctypes.POINTER(fast_plane)), ("levels", ctypes.c_int32),
+                ("t", ctypes.c_int32), ("n", ctypes.c_int32), ("cell", ctypes.c_int32),
+                ("out", ctypes.c_void_p)]
+
+
+class FastError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {code} ({detail})" if detail else f"{what}: {code}")
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the HIP library.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} missing: build it with __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i32, u64p = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)
+        P = ctypes.POINTER(fast_plane)
+        sig = {
+            "fast_ctx_create": ([i32, ctypes.POINTER(vp)], i32),
+            "fast_ctx_destroy": ([vp], None),
+            "fast_strerror": ([i32], ctypes.c_char_p),
+            "fast_last_error": ([vp], ctypes.c_char_p),
+            "fast_pyr_dims": ([i32, i32, i32, P], i32),
+            "fast_grid_dims": ([i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+            "fast_pyr_build": ([vp, P, i32, vp], i32),
+            "fast_detect_grid": ([vp, P, i32, i32, i32, i32, vp, vp], i32),
+            "fast_submit": ([vp, ctypes.POINTER(fast_job), i32, vp, u64p], i32),
+            "fast_poll": ([vp, ctypes.c_uint64], i32),
+            "fast_wait": ([vp, ctypes.c_uint64, i32], i32),
+            "fast_plan_create": ([vp, ctypes.POINTER(fast_job), i32, ctypes.POINTER(i32)], i32),
+            "fast_plan_launch": ([vp, i32, vp, u64p], i32),
+            "fast_plan_destroy": ([vp, i32], i32),
+            "fast_set_launch": ([vp, i32, i32, i32], i32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = lib
+    return _lib
+
+
+def _check(ctx, rc: int, what: str) -> int:
+    if rc < 0:
+        detail = load().fast_last_error(ctx).decode() if ctx else load().fast_strerror(rc).decode()
+        raise FastError(rc, what, detail)
+    return rc
+
+
+# ------------------------------------------------------------- C entry points
+
+def fast_ctx_create(device: int = 0) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    rc = load().fast_ctx_create(device, ctypes.byref(h))
+    if rc < 0:
+        raise FastError(rc, "fast_ctx_create", load().fast_strerror(rc).decode())
+    return h
+
+
+def fast_ctx_destroy(ctx) -> None:
+    load().fast_ctx_destroy(ctx)
+
+
+def fast_pyr_dims(width: int, height: int, levels: int) -> list[tuple[int, int, int]]:
+    arr = (fast_plane * levels)()
+    rc = load().fast_pyr_dims(width, height, levels, arr)
+    if rc < 0:
+        raise FastError(rc, "fast_pyr_dims")
+    return [(p.width, p.height, p.pitch) for p in arr]
+
+
+def fast_grid_dims(width: int, height: int, cell: int) -> tuple[int, int]:
+    gw, gh = ctypes.c_int(), ctypes.c_int()
+    rc = load().fast_grid_dims(width, height, cell, ctypes.byref(gw), ctypes.byref(gh))
+    if rc < 0:
+        raise FastError(rc, "fast_grid_dims")
+    return gw.value, gh.value
+
+
+def fast_pyr_build(ctx, planes, levels: int, stream=None) -> None:
+    _check(ctx, load().fast_pyr_build(ctx, planes, levels, _stream(stream)), "fast_pyr_build")
+
+
+def fast_detect_grid(ctx, planes, levels: int, t: int, n: int, cell: int, out_ptr: int,
+                     stream=None) -> None:
+    _check(ctx, load().fast_detect_grid(ctx, planes, levels, t, n, cell, out_ptr,
+                                        _stream(stream)), "fast_detect_grid")
+
+
+def fast_submit(ctx, jobs, njobs: int, stream=None) -> int:
+    tk = ctypes.c_uint64()
+    _check(ctx, load().fast_submit(ctx, jobs, njobs, _stream(stream), ctypes.byref(tk)),
+           "fast_submit")
+    return tk.value
+
+
+def fast_poll(ctx, ticket: int) -> bool:
+    return _check(ctx, load().fast_poll(ctx, ticket), "fast_poll") == 1
+
+
+def fast_wait(ctx, ticket: int, timeout_ms: int = -1) -> bool:
+    """True when finished, False on time-out."""
+    rc = load().fast_wait(ctx, ticket, timeout_ms)
+    if rc == FAST_ETIMEDOUT:
+        return False
+    _check(ctx, rc, "fast_wait")
+    return True
+
+
+def fast_plan_create(ctx, jobs, njobs: int) -> int:
+    pid = ctypes.c_int()
+    _check(ctx, load().fast_plan_create(ctx, jobs, njobs, ctypes.byref(pid)), "fast_plan_create")
+    return pid.value
+
+
+def fast_plan_launch(ctx, plan_id: int, stream=None) -> int:
+    tk = ctypes.c_uint64()
+    _check(ctx, load().fast_plan_launch(ctx, plan_id, _stream(stream), ctypes.byref(tk)),
+           "fast_plan_launch")
+    return tk.value
+
+
+def fast_plan_destroy(ctx, plan_id: int) -> None:
+    _check(ctx, load().fast_plan_destroy(ctx, plan_id), "fast_plan_destroy")
+
+
+def fast_set_launch(ctx, region: int, block: int, blocks_per_cu: int) -> None:
+    _check(ctx, load().fast_set_launch(ctx, region, block, blocks_per_cu), "fast_set_launch")
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------- torch helpers
+
+class Pyramid:
+    """Device planes of one frame's pyramid, owned by torch tensors."""
+
+    def __init__(self, width: int, height: int, levels: int, device="cuda"):
+        import torch
+        self.width, self.height, self.levels = width, height, levels
+        self.dims = fast_pyr_dims(width, height, levels)
+        self.tensors = [torch.zeros((h, p), dtype=torch.uint8, device=device)
+                        for (w, h, p) in self.dims]
+        self.planes = (fast_plane * levels)(*[
+            fast_plane(t.data_ptr(), w, h, p) for t, (w, h, p) in zip(self.tensors, self.dims)])
+
+    def upload(self, img: np.ndarray, non_blocking: bool = False) -> None:
+        """Copy a (height, >=width) uint8 host image into level 0."""
+        import torch
+        p = self.dims[0][2]
+        src = np.zeros((self.height, p), np.uint8)
+        cols = min(p, img.shape[1])
+        src[:, :cols] = img[:, :cols]
+        self.tensors[0].copy_(torch.from_numpy(src), non_blocking=non_blocking)
+
+    def level(self, k: int) -> np.ndarray:
+        w, h, _ = self.dims[k]
+        return self.tensors[k][:, :w].cpu().numpy()
+
+
+class Grid:
+    """Device array of cell slots for one frame."""
+
+    def __init__(self, width: int, height: int, cell: int, device="cuda"):
+        import torch
+        self.gw, self.gh = fast_grid_dims(width, height, cell)
+        self.tensor = torch.zeros(self.gw * self.gh * 8, dtype=torch.uint8, device=device)
+
+    @property
+    def ptr(self) -> int:
+        return self.tensor.data_ptr()
+
+    def fetch(self) -> np.ndarray:
+        return self.tensor.cpu().numpy().view(FEATURE_DTYPE)
+
+
+class Context:
+    """Owns a fast_ctx; detect() is the plain path, submit()/plan_*() the batched one."""
+
+    def __init__(self, device: int = 0):
+        self.handle = fast_ctx_create(device)
+
+    def close(self):
+        if self.handle:
+            fast_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_launch(self, region: int, block: int, blocks_per_cu: int) -> None:
+        fast_set_launch(self.handle, region, block, blocks_per_cu)
+
+    def pyr_build(self, pyr: Pyramid, stream=None) -> None:
+        fast_pyr_build(self.handle, pyr.planes, pyr.levels, stream)
+
+    def detect(self, pyr: Pyramid, t: int, n: int, cell: int, grid: Grid, stream=None) -> None:
+        fast_detect_grid(self.handle, pyr.planes, pyr.levels, t, n, cell, grid.ptr, stream)
+
+    @staticmethod
+    def make_jobs(items) -> ctypes.Array:
+        """items: iterable of (Pyramid, t, n, cell, Grid)."""
+        items = list(items)
+        arr = (fast_job * len(items))()
+        for i, (pyr, t, n, cell, grid) in enumerate(items):
+            arr[i] = fast_job(ctypes.cast(pyr.planes, ctypes.POINTER(fast_plane)), pyr.levels,
+                              t, n, cell, grid.ptr)
+        return arr
+
+    def submit(self, jobs: ctypes.Array, stream=None) -> int:
+        return fast_submit(self.handle, jobs, len(jobs), stream)
+
+    def poll(self, ticket: int) -> bool:
+        return fast_poll(self.handle, ticket)
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> bool:
+        return fast_wait(self.handle, ticket, timeout_ms)
+
+    def plan_create(self, jobs: ctypes.Array) -> int:
+        return fast_plan_create(self.handle, jobs, len(jobs))
+
+    def plan_launch(self, plan_id: int, stream=None) -> int:
+        return fast_plan_launch(self.handle, plan_id, stream)
+
+    def plan_destroy(self, plan_id: int) -> None:
+        fast_plan_destroy(self.handle, plan_id)

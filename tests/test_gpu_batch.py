@@ -1,0 +1,136 @@
+"""GPU parity of the batched entry points (persistent launch over a device work
+queue, and graph-captured resident batches) against the oracle and against
+the plain one-frame path."""
+import numpy as np
+import pytest
+
+import oracle
+from conftest import as_tuples
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2003_13493_amd import fastgrid, synth  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available()
+    c = fastgrid.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def batch():
+    """The uneven 64-frame batch with its oracle answers."""
+    specs = synth.batch64()
+    frames = [s.make() for s in specs]
+    want = []
+    for s, img in zip(specs, frames):
+        slots, planes = oracle.detect_grid(img, s.width, s.levels, s.t, s.n, s.cell)
+        want.append((slots, [p[:, :w].copy() for p, w in planes]))
+    return specs, frames, want
+
+
+def make_resident(specs, frames):
+    pyrs, grids = [], []
+    for s, img in zip(specs, frames):
+        p = fastgrid.Pyramid(s.width, s.height, s.levels)
+        p.upload(img)
+        pyrs.append(p)
+        grids.append(fastgrid.Grid(s.width, s.height, s.cell))
+    jobs = fastgrid.Context.make_jobs((p, s.t, s.n, s.cell, g) for p, s, g in zip(pyrs, specs, grids))
+    return pyrs, grids, jobs
+
+
+def check_all(specs, pyrs, grids, want, tag):
+    for i, (s, p, g) in enumerate(zip(specs, pyrs, grids)):
+        slots, planes = want[i]
+        for k in range(1, s.levels):
+            assert np.array_equal(p.level(k), planes[k]), f"{tag} frame {i} level {k}"
+        got = g.fetch()
+        if not np.array_equal(got, slots):
+            gt, wt = as_tuples(got), as_tuples(slots)
+            bad = [c for c in range(len(gt)) if gt[c] != wt[c]]
+            raise AssertionError(f"{tag} frame {i} ({s.width}x{s.height} t={s.t} n={s.n} "
+                                 f"cell={s.cell}): {len(bad)} cells differ, e.g. {bad[:3]}")
+
+
+def test_submit_batch64_bit_exact(ctx, batch):
+    specs, frames, want = batch
+    print("case submit batch64", flush=True)
+    pyrs, grids, jobs = make_resident(specs, frames)
+    tk = ctx.submit(jobs)
+    assert ctx.wait(tk, 60_000)
+    assert ctx.poll(tk)
+    check_all(specs, pyrs, grids, want, "submit")
+
+
+def test_submit_back_to_back_reuses_queue(ctx, batch):
+    """Several submissions in a row: the self-resetting queue counter must be
+    re-armed by each launch."""
+    specs, frames, want = batch
+    sel = list(range(0, 64, 5))
+    sp = [specs[i] for i in sel]
+    pyrs, grids, jobs = make_resident(sp, [frames[i] for i in sel])
+    tickets = []
+    for r in range(6):
+        for g in grids:
+            g.tensor.fill_(0xAB)
+        tickets.append(ctx.submit(jobs))
+        assert ctx.wait(tickets[-1], 60_000)
+        check_all(sp, pyrs, grids, [want[i] for i in sel], f"round {r}")
+    assert all(ctx.poll(t) for t in tickets)
+
+
+def test_plan_graph_replays(ctx, batch):
+    specs, frames, want = batch
+    print("case plan replays", flush=True)
+    pyrs, grids, jobs = make_resident(specs, frames)
+    pid = ctx.plan_create(jobs)
+    try:
+        for r in range(4):
+            for g in grids:
+                g.tensor.fill_(0x5A)
+            for p in pyrs:
+                for t in p.tensors[1:]:
+                    t.fill_(0)
+            torch.cuda.synchronize()
+            tk = ctx.plan_launch(pid)
+            assert ctx.wait(tk, 60_000)
+            check_all(specs, pyrs, grids, want, f"replay {r}")
+    finally:
+        ctx.plan_destroy(pid)
+
+
+def test_batch_equals_plain_per_frame(ctx, batch):
+    specs, frames, _ = batch
+    sel = [0, 7, 13, 40, 63]
+    sp = [specs[i] for i in sel]
+    pyrs, grids, jobs = make_resident(sp, [frames[i] for i in sel])
+    tk = ctx.submit(jobs)
+    assert ctx.wait(tk, 60_000)
+    for s, i, g in zip(sp, sel, grids):
+        p = fastgrid.Pyramid(s.width, s.height, s.levels)
+        p.upload(frames[i])
+        g2 = fastgrid.Grid(s.width, s.height, s.cell)
+        ctx.detect(p, s.t, s.n, s.cell, g2)
+        torch.cuda.synchronize()
+        assert np.array_equal(g.fetch(), g2.fetch())
+
+
+def test_submit_rejects_bad_job_and_enqueues_nothing(ctx, batch):
+    specs, frames, _ = batch
+    sp = specs[:3]
+    pyrs, grids, jobs = make_resident(sp, frames[:3])
+    jobs[1].n = 0
+    with pytest.raises(fastgrid.FastError) as ei:
+        ctx.submit(jobs)
+    assert ei.value.code == fastgrid.FAST_EINVAL
+
+
+def test_poll_unknown_ticket(ctx):
+    with pytest.raises(fastgrid.FastError):
+        ctx.poll(10 ** 12)
