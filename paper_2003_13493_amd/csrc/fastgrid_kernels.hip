@@ -1,129 +1,628 @@
 // Device code of libfastgrid: pyramid, FAST score, 3x3 NMS and per-cell
 // arg-max over all pyramid levels ("Faster than FAST", Sections II-B to II-D).
 //
-// Work decomposition: a workgroup owns a square region of whole grid cells.
-// For every level it walks the region's level-k footprint in sub-tiles,
-// stages each sub-tile (plus a 4-pixel halo: 3 for the circle, 1 for the NMS
-// neighbours) in LDS, scores it, suppresses non-maxima, and folds survivors
-// into one 32-bit key per cell with an LDS atomicMax.  The key orders
-// candidates by (score desc, level asc, row-major index asc), so a single max
-// is the cell's answer, independent of the order threads arrive in.
+// Work decomposition
+// ------------------
+// A workgroup owns a region of whole grid cells (a multiple of 16 level-0
+// pixels wide and tall) and walks it in 64x64 level-0 sub-tiles.  For pyramids
+// of up to 3 levels the sub-tile is loaded once with a 4*2^(L-1)-pixel halo and
+// the deeper levels are built from it in LDS (one pass over HBM: level 0 read
+// once, levels 1.. written once).  Deeper pyramids are built by a separate
+// kernel and each level's sub-tile is loaded with a 4-pixel halo.
+//
+// Detection inside a sub-tile is split into row strips (<= 16 rows plus a
+// 1-row ring above and below), one strip at a time per wave, with no
+// workgroup barrier: every strip computes the scores of its own ring rows, so
+// a wave never waits for another.  Per strip:
+//
+//   P1 compass test, all pixels, 8 per lane in packed 16-bit lanes.  An arc of
+//      N circle pixels contains floor(N/4) consecutive compass points (circle
+//      indices 0, 4, 8, 12) of its label.  Result: one flag bit per pixel.
+//   P2 compaction of the survivors into a wave-private LDS list (DPP prefix
+//      scan of per-lane counts).
+//   P3 8-point test, one survivor per lane: the arc also contains floor(N/2)
+//      consecutive even circle points of its label.  In-place compaction
+//      (ballot + mbcnt).
+//   P4 full segment test and score (Section II-D, Eq. (1)) into the level's
+//      score map (a 1-pixel ring around the sub-tile, shared by the strips).
+//   P5 3x3 NMS (Section I-B, n=1) of the strip's own rows and an LDS atomicMax
+//      of a 32-bit key per cell: (score << 19) | ((7-level) << 16) |
+//      (0xFFFF - row-major index inside the cell), which orders candidates by
+//      (score desc, level asc, index asc), so the cell's answer does not
+//      depend on thread order.
+//
+// Both filters are necessary conditions of the segment test, so a pixel they
+// reject has score 0; the cascade never changes a result.
 #include "fg_internal.h"
 
 namespace {
 
-constexpr int SUB = 64;                 // sub-tile side (level-k pixels)
-constexpr int HALO = 4;                 // 3 (circle) + 1 (NMS neighbour)
-constexpr int TILE_W = SUB + 2 * HALO;  // 72
-constexpr int TILE_P = 80;              // LDS row pitch of the pixel tile
-constexpr int SC_W = SUB + 2;           // scores: sub-tile plus 1-pixel ring
-constexpr int SC_P = 68;
-constexpr int MAX_RCELLS = 32;          // cells per region side
+constexpr int SUB = 64;                 // sub-tile side at level 0
+constexpr int MAX_FUSED = 3;            // levels built in LDS from one load
+
+// All level tiles share one LDS row pitch, so circle offsets are constants.
+// Band A (rows 0..95): level 0 of a fused sub-tile, or the current level of an
+// unfused one.  Band B (rows 96..143): level 1 at byte 8, level 2 at byte 64.
+constexpr int LP = 112;
+constexpr int T0 = 16;
+constexpr int T1 = 96 * LP + 8;
+constexpr int T2 = 96 * LP + 64;
+constexpr int TILE_BYTES = 144 * LP;
+static_assert(T0 % 16 == 0 && LP % 16 == 0, "16-byte tile stores in band A");
+static_assert(T1 % 8 == 0 && T2 % 4 == 0, "8-byte reads when halving level 1");
+static_assert(TILE_BYTES <= 16384, "entries hold 14-bit LDS offsets");
+// Score maps: a level's sub-tile area plus a 1-pixel ring.
+constexpr int M0_ROWS = SUB + 2, M0_P = SUB + 4;
+constexpr int M1_ROWS = SUB / 2 + 2, M1_P = SUB / 2 + 4;
+constexpr int M2_ROWS = SUB / 4 + 2, M2_P = SUB / 4 + 4;
+constexpr int MAX_RCELLS = 16;
 constexpr int MAX_KEYS = MAX_RCELLS * MAX_RCELLS;
+// Per-wave scratch: the candidate list of one part (<= 18 scored rows of each
+// level: 18*72 + 10*40 + 6*24 = 1840 pixels).
+constexpr int LIST_CAP = 1856;
+constexpr uint16_t NO_ENTRY = 0xFFFF;
 
-// Circle of radius 3 (Section II-D), cyclic order.
-__constant__ int8_t c_dx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
-__constant__ int8_t c_dy[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
+constexpr int OFF_M0 = TILE_BYTES;
+constexpr int OFF_M1 = OFF_M0 + M0_ROWS * M0_P * 2;
+constexpr int OFF_M2 = OFF_M1 + M1_ROWS * M1_P * 2;
+constexpr int OFF_KEYS = (OFF_M2 + M2_ROWS * M2_P * 2 + 15) & ~15;
+constexpr int OFF_WAVES = OFF_KEYS + MAX_KEYS * 4;
+constexpr int WAVE_BYTES = LIST_CAP * 2;
+static_assert(OFF_WAVES % 16 == 0 && WAVE_BYTES % 16 == 0, "aligned scratch");
 
-// Circular run of >= n set bits in a 16-bit mask: AND shifted copies of the
-// doubled mask, doubling the covered length each step.
-__device__ __forceinline__ bool has_arc(uint32_t m, int n) {
-    uint32_t r = m | (m << 16);
-    int have = 1;
-    while (have * 2 <= n) {
-        r &= r >> have;
-        have *= 2;
-    }
-    if (have < n) r &= r >> (n - have);
-    return (r & 0xFFFFu) != 0;
+}  // namespace
+
+size_t fg_smem_bytes(int block) { return (size_t)OFF_WAVES + (size_t)(block / 64) * WAVE_BYTES; }
+
+namespace {
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ s16x2 as_s16x2(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
+__device__ __forceinline__ uint32_t as_u32(s16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ s16x2 vmax(s16x2 a, s16x2 b) { return __builtin_elementwise_max(a, b); }
+__device__ __forceinline__ s16x2 vmin(s16x2 a, s16x2 b) { return __builtin_elementwise_min(a, b); }
+
+// Two bytes of the 8-byte value {hi, lo} zero-extended into 16-bit lanes.
+__device__ __forceinline__ s16x2 pair(uint32_t hi, uint32_t lo, uint32_t sel) {
+    return as_s16x2(__builtin_amdgcn_perm(hi, lo, sel));
 }
 
-// Score of the pixel at tile position (lx, ly); caller guarantees the 7x7
-// stencil lies inside the tile and the pixel is outside the 3-pixel border.
-__device__ __forceinline__ uint32_t fast_score(const uint8_t *tile, int lx, int ly, int t,
-                                               int n) {
-    const int c = tile[ly * TILE_P + lx];
-    const int hi = c + t, lo = c - t;
-    uint32_t bm = 0, dm = 0;
-    int sb = 0, sd = 0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int p = tile[(ly + c_dy[i]) * TILE_P + lx + c_dx[i]];
-        const int db = p - hi, dd = lo - p;
-        bm |= (db > 0 ? 1u : 0u) << i;
-        dm |= (dd > 0 ? 1u : 0u) << i;
-        sb += db > 0 ? db : 0;
-        sd += dd > 0 ? dd : 0;
+__device__ __forceinline__ int lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// Orders this wave's LDS accesses across its lanes (LDS executes one wave's
+// operations in order; this keeps the compiler from reordering them).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Inclusive prefix sum over the 64 lanes: shifts within rows of 16 lanes,
+// then the row totals are broadcast into the following rows.
+__device__ __forceinline__ int wave_scan(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return x;
+}
+
+// Bit i of the result is set iff bits i..i+n-1 of m are all set (n >= 1).
+__device__ __forceinline__ uint32_t runs(uint32_t m, int n) {
+    int have = 1;
+    while (have * 2 <= n) {
+        m &= m >> have;
+        have *= 2;
     }
-    if (!has_arc(bm, n) && !has_arc(dm, n)) return 0;
+    if (have < n) m &= m >> (n - have);
+    return m;
+}
+
+// Compass test of two pixels in packed 16-bit lanes; per lane >= 0 iff the
+// pixel may be a corner.  K = floor(N/4) consecutive points of (N, E, S, W)
+// must all be brighter than c+t (darker than c-t); the weakest value over the
+// best run is compared with the centre.
+template <int K>
+__device__ __forceinline__ s16x2 compass(s16x2 C, s16x2 N, s16x2 E, s16x2 S, s16x2 W, s16x2 T1) {
+    s16x2 need_hi, need_lo;
+    if constexpr (K == 1) {
+        need_hi = vmax(vmax(N, S), vmax(E, W));
+        need_lo = vmin(vmin(N, S), vmin(E, W));
+    } else if constexpr (K == 2) {
+        // adjacent pairs (N,E) (E,S) (S,W) (W,N): (N or S) and (E or W)
+        need_hi = vmin(vmax(N, S), vmax(E, W));
+        need_lo = vmax(vmin(N, S), vmin(E, W));
+    } else if constexpr (K == 3) {
+        // any 3 of the 4 are consecutive: second smallest / second largest
+        const s16x2 lo1 = vmin(N, S), hi1 = vmax(N, S), lo2 = vmin(E, W), hi2 = vmax(E, W);
+        need_hi = vmin(vmax(lo1, lo2), vmin(hi1, hi2));
+        need_lo = vmax(vmin(hi1, hi2), vmax(lo1, lo2));
+    } else {
+        need_hi = vmin(vmin(N, S), vmin(E, W));
+        need_lo = vmax(vmax(N, S), vmax(E, W));
+    }
+    return vmax(need_hi - C, C - need_lo) - T1;
+}
+
+// Circle of radius 3 (Section II-D) in cyclic order, as LDS byte offsets.
+#define CIRC(j) (CDY[j] * LP + CDX[j])
+constexpr int CDX[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
+constexpr int CDY[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
+
+// Full segment test and score (Eq. (1)) of the pixel at p.  Sums use
+// max(x,0) = (x + |x|)/2 over the whole circle.
+__device__ __forceinline__ uint32_t full_score(const uint8_t *p, int t, int n) {
+    const int cv = p[0];
+    const int hi = cv + t;
+    const int lo = cv - t > 0 ? cv - t : 0;   // darker needs v < c-t; none if c-t <= 0
+    uint32_t bm = 0, dm = 0;
+    int sum = 0, ab = 0, ad = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int v = p[CIRC(j)];
+        bm = __builtin_amdgcn_alignbit(bm, (uint32_t)(hi - v), 31);
+        dm = __builtin_amdgcn_alignbit(dm, (uint32_t)(v - lo), 31);
+        sum += v;
+        ab += v > hi ? v - hi : hi - v;
+        ad += v > lo ? v - lo : lo - v;
+    }
+    const uint32_t b2 = bm | (bm << 16), d2 = dm | (dm << 16);
+    if (((runs(b2, n) | runs(d2, n)) & 0xFFFFu) == 0) return 0;
+    const int sb = (sum - 16 * hi + ab) >> 1;
+    const int sd = (16 * lo - sum + ad) >> 1;
     return (uint32_t)(sb > sd ? sb : sd);
 }
 
-// Cell key: (score << 19) | ((7 - level) << 16) | (0xFFFF - local index).
-__device__ __forceinline__ uint32_t make_key(uint32_t score, int level, uint32_t local) {
-    return (score << 19) | ((uint32_t)(7 - level) << 16) | (0xFFFFu - local);
+// One pyramid level of the current sub-tile as staged in LDS (uniform).
+struct Geo {
+    int tbase;           // LDS offset of tile (0,0)
+    int tx, ty;          // level coordinates of tile (0,0)
+    int W, H;            // level size
+    int sx, sy, ex, ey;  // sub-tile area at this level (NMS targets), clipped
+    int moff, mp;        // score map: LDS offset and pitch (u16) of [sx-1, ex+1) x [sy-1, ey+1)
+    int gc0, ncolg;      // first group column (tile coords) and groups per row (even)
+    int k;               // level index
+};
+
+struct Params {
+    int t, n, kc, k8;    // threshold, arc length, floor(N/4), floor(N/2)
+    int cell;            // level-0 cell side
+    int rx0, ry0;        // region origin in level-0 pixels
+    int ncx;             // cells across the region
+};
+
+__device__ __forceinline__ void set_groups(Geo &g) {
+    const int c_first = g.sx - 1 - g.tx;
+    g.gc0 = c_first & ~3;
+    g.ncolg = (g.ex + 1 - g.tx - g.gc0 + 3) >> 2;
+    g.ncolg += g.ncolg & 1;   // whole pairs of groups
 }
 
-__device__ void detect_region(const fg_job &J, int region, uint8_t *tile, uint16_t *sc,
-                              uint32_t *keys) {
-    const int tid = threadIdx.x, nthr = blockDim.x;
+__device__ __forceinline__ bool has_area(const Geo &g) { return g.ex > g.sx && g.ey > g.sy; }
+
+// Row and column-pair of item i of a segment with ppr pairs per row (i < 256,
+// ppr <= 9): the float quotient is exact in this range.
+__device__ __forceinline__ int item_row(int i, float inv_ppr) {
+    return (int)(((float)i + 0.5f) * inv_ppr);
+}
+
+// P1+P2 for one segment: compass test of every scored pixel (8 per lane,
+// packed 16-bit lanes), survivors kept as bits in a register, then appended
+// to the list with one wave prefix sum.  Entries are (level << 14) | (LDS
+// offset of the pixel); pixels outside the testable area (3 <= x <= W-4,
+// 3 <= y <= H-4, inside the scored ring) become NO_ENTRY.  Returns the new
+// count (wave-uniform).
+template <int K>
+__device__ int seg_collect(const uint8_t *smem, int tbase, int r_first, int nrows, int gc0, int ncolg,
+                           int t, uint32_t tag, int c_lo, int c_hi, int r_lo, int r_hi,
+                           uint16_t *list, int count) {
+    const int lane = lane_id();
+    const int ppr = ncolg >> 1;                 // pairs of groups (8 pixels) per row
+    const int total = nrows * ppr;              // <= 18 * 9: at most 3 rounds of 64
+    const float inv_ppr = 1.0f / (float)ppr;
+    const s16x2 T1 = {(short)(t + 1), (short)(t + 1)};
+    const uint8_t *tile = smem + tbase;
+    uint32_t bits = 0;                          // 8 bits per round: bit 4h+b = pixel 2b+h
+#pragma unroll
+    for (int round = 0; round < 4; ++round) {
+        const int i = lane + 64 * round;
+        if (64 * round >= total) break;
+        uint32_t sv = 0;
+        if (i < total) {
+            if constexpr (K > 0) {
+                const int row = item_row(i, inv_ppr), pp = i - row * ppr;
+                const uint8_t *p = tile + (r_first + row) * LP + gc0 + 8 * pp;
+                const uint32_t D0 = *(const uint32_t *)(p - 4);
+                const uint32_t D1 = *(const uint32_t *)(p);
+                const uint32_t D2 = *(const uint32_t *)(p + 4);
+                const uint32_t D3 = *(const uint32_t *)(p + 8);
+                const uint32_t N0 = *(const uint32_t *)(p - 3 * LP);
+                const uint32_t N1 = *(const uint32_t *)(p - 3 * LP + 4);
+                const uint32_t S0 = *(const uint32_t *)(p + 3 * LP);
+                const uint32_t S1 = *(const uint32_t *)(p + 3 * LP + 4);
+                const uint32_t r01 = as_u32(compass<K>(
+                    pair(D1, D1, 0x0c010c00u), pair(N0, N0, 0x0c010c00u), pair(D2, D1, 0x0c040c03u),
+                    pair(S0, S0, 0x0c010c00u), pair(D1, D0, 0x0c020c01u), T1));
+                const uint32_t r23 = as_u32(compass<K>(
+                    pair(D1, D1, 0x0c030c02u), pair(N0, N0, 0x0c030c02u), pair(D2, D1, 0x0c060c05u),
+                    pair(S0, S0, 0x0c030c02u), pair(D1, D0, 0x0c040c03u), T1));
+                const uint32_t r45 = as_u32(compass<K>(
+                    pair(D2, D2, 0x0c010c00u), pair(N1, N1, 0x0c010c00u), pair(D3, D2, 0x0c040c03u),
+                    pair(S1, S1, 0x0c010c00u), pair(D2, D1, 0x0c020c01u), T1));
+                const uint32_t r67 = as_u32(compass<K>(
+                    pair(D2, D2, 0x0c030c02u), pair(N1, N1, 0x0c030c02u), pair(D3, D2, 0x0c060c05u),
+                    pair(S1, S1, 0x0c030c02u), pair(D2, D1, 0x0c040c03u), T1));
+                // sign bit of each 16-bit lane = rejected; gather the 8 signs
+                uint32_t sg = ((r01 >> 15) & 0x10001u) | ((r23 >> 14) & 0x20002u) |
+                              ((r45 >> 13) & 0x40004u) | ((r67 >> 12) & 0x80008u);
+                sv = ~(sg | (sg >> 12)) & 0xFFu;
+            } else {
+                sv = 0xFFu;
+            }
+        }
+        bits |= sv << (8 * round);
+    }
+    const int cnt = __builtin_popcount(bits);
+    const int incl = wave_scan(cnt);
+    int pos = count + incl - cnt;
+    count += __builtin_amdgcn_readlane(incl, 63);
+    while (bits) {
+        const int b = __builtin_ctz(bits);
+        bits &= bits - 1;
+        const int i = lane + 64 * (b >> 3);
+        const int row = item_row(i, inv_ppr), pp = i - row * ppr;
+        const int r = r_first + row;
+        const int q = ((b & 3) << 1) | ((b >> 2) & 1);
+        const int c = gc0 + 8 * pp + q;
+        const uint16_t e = r >= r_lo && r <= r_hi && c >= c_lo && c <= c_hi
+                               ? (uint16_t)((tag << 14) | (uint32_t)(tbase + r * LP + c))
+                               : NO_ENTRY;
+        if (pos < LIST_CAP) list[pos] = e;
+        ++pos;
+    }
+    return count < LIST_CAP ? count : LIST_CAP;
+}
+
+// P3: keep entries that pass the 8-point test, compacted in place.
+__device__ int pass_even8(const uint8_t *smem, int t, int k8, uint16_t *list, int n1) {
+    const int lane = lane_id();
+    int n2 = 0;
+    for (int i0 = 0; i0 < n1; i0 += 64) {
+        const int i = i0 + lane;
+        bool pass = false;
+        uint16_t e = NO_ENTRY;
+        if (i < n1) e = list[i];
+        if (e != NO_ENTRY) {
+            const uint8_t *p = smem + (e & 0x3FFF);
+            const int cv = p[0];
+            const int hi = cv + t, lo = cv - t;
+            uint32_t bm = 0, dm = 0;
+#pragma unroll
+            for (int j = 0; j < 16; j += 2) {
+                const int v = p[CIRC(j)];
+                bm = __builtin_amdgcn_alignbit(bm, (uint32_t)(hi - v), 31);
+                dm = __builtin_amdgcn_alignbit(dm, (uint32_t)(v - lo), 31);
+            }
+            pass = k8 == 0 ||
+                   ((runs(bm | (bm << 8), k8) | runs(dm | (dm << 8), k8)) & 0xFFu) != 0;
+        }
+        const uint64_t bal = __ballot(pass);
+        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        if (pass) list[n2 + rank] = e;
+        n2 += __popcll(bal);
+        wave_sync();
+    }
+    return n2;
+}
+
+__device__ __forceinline__ int sel3(int l, int a, int b, int c) { return l == 0 ? a : (l == 1 ? b : c); }
+
+// Row and column inside the LDS tile band of an entry's offset.
+__device__ __forceinline__ void tile_rc(uint32_t off, int &row, int &col) {
+    row = (int)((off * 18725u) >> 21);   // off / LP, exact for off < 16384
+    col = (int)off - row * LP;
+}
+
+// Per-level constants for mapping an entry to its score map and cell.
+struct LevelMap {
+    int mp, mbias;       // map index = row * mp + col + mbias (row, col in the tile band)
+    int rlo, rhi;        // band rows this pass owns for NMS: [rlo, rhi)
+    int clo, chi;        // band columns of the sub-tile area: [clo, chi)
+    int xo, yo;          // cell-relative position = (col + xo, row + yo)
+    int cw;              // cell side at this level
+};
+
+__device__ __forceinline__ LevelMap level_map(const Geo &g, int band_row, int band_col, int ra,
+                                             int rb, const Params &P) {
+    LevelMap m;
+    const int ybias = g.ty - band_row, xbias = g.tx - band_col;   // level y = row + ybias
+    m.mp = g.mp;
+    m.mbias = (g.moff >> 1) + (ybias - (g.sy - 1)) * g.mp + (xbias - (g.sx - 1));
+    m.rlo = ra - ybias;
+    m.rhi = rb - ybias;
+    m.clo = g.sx - xbias;
+    m.chi = g.ex - xbias;
+    m.xo = xbias - (P.rx0 >> g.k);
+    m.yo = ybias - (P.ry0 >> g.k);
+    m.cw = P.cell >> g.k;
+    return m;
+}
+
+// One pass of a wave: segments [ra_l, rb_l) of up to three levels (empty
+// when ra_l == rb_l), each scored with a 1-row ring.  P1..P5 run once over
+// the whole pass.
+__device__ void process_pass(uint8_t *smem, const Geo &g0, const Geo &g1, const Geo &g2,
+                             const int ra[3], const int rb[3], const Params &P, uint16_t *list,
+                             uint32_t *keys) {
+    const Geo *gs[3] = {&g0, &g1, &g2};
+    int n1 = 0;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        if (ra[l] >= rb[l]) continue;
+        const Geo &g = *gs[l];
+        const int r_first = ra[l] - 1 - g.ty;
+        const int nrows = rb[l] - ra[l] + 2;
+        const int c_lo = max(g.sx - 1, 3) - g.tx, c_hi = min(g.ex, g.W - 4) - g.tx;
+        const int r_lo = max(r_first, 3 - g.ty);
+        const int r_hi = min(r_first + nrows - 1, g.H - 4 - g.ty);
+#define FG_COLLECT(KK) n1 = seg_collect<KK>(smem, g.tbase, r_first, nrows, g.gc0, g.ncolg, P.t, \
+                                            (uint32_t)l, c_lo, c_hi, r_lo, r_hi, list, n1)
+        switch (P.kc) {
+            case 0: FG_COLLECT(0); break;
+            case 1: FG_COLLECT(1); break;
+            case 2: FG_COLLECT(2); break;
+            case 3: FG_COLLECT(3); break;
+            default: FG_COLLECT(4); break;
+        }
+#undef FG_COLLECT
+    }
+    wave_sync();
+    const int n2 = pass_even8(smem, P.t, P.k8, list, n1);
+    const LevelMap m0 = level_map(g0, 0, T0, ra[0], rb[0], P);
+    const LevelMap m1 = level_map(g1, 96, T1 - 96 * LP, ra[1], rb[1], P);
+    const LevelMap m2 = level_map(g2, 96, T2 - 96 * LP, ra[2], rb[2], P);
+    uint16_t *maps = (uint16_t *)smem;
+    const int lane = lane_id();
+    for (int i = lane; i < n2; i += 64) {
+        const uint16_t e = list[i];
+        const uint32_t s = full_score(smem + (e & 0x3FFF), P.t, P.n);
+        if (s) {
+            const int l = e >> 14;
+            int row, col;
+            tile_rc(e & 0x3FFF, row, col);
+            maps[row * sel3(l, m0.mp, m1.mp, m2.mp) + col + sel3(l, m0.mbias, m1.mbias, m2.mbias)] =
+                (uint16_t)s;
+        }
+    }
+    wave_sync();
+    for (int i = lane; i < n2; i += 64) {
+        const uint16_t e = list[i];
+        const int l = e >> 14;
+        int row, col;
+        tile_rc(e & 0x3FFF, row, col);
+        if (row < sel3(l, m0.rlo, m1.rlo, m2.rlo) || row >= sel3(l, m0.rhi, m1.rhi, m2.rhi) ||
+            col < sel3(l, m0.clo, m1.clo, m2.clo) || col >= sel3(l, m0.chi, m1.chi, m2.chi))
+            continue;   // ring pixel: another pass owns its suppression
+        const int mp = sel3(l, m0.mp, m1.mp, m2.mp);
+        const uint16_t *q = maps + row * mp + col + sel3(l, m0.mbias, m1.mbias, m2.mbias);
+        const uint32_t s = q[0];
+        if (s == 0) continue;
+        // earlier neighbours in row-major order must be strictly lower,
+        // later ones lower or equal
+        const bool keep = s > q[-mp - 1] && s > q[-mp] && s > q[-mp + 1] && s > q[-1] &&
+                          s >= q[1] && s >= q[mp - 1] && s >= q[mp] && s >= q[mp + 1];
+        if (!keep) continue;
+        const int cw = sel3(l, m0.cw, m1.cw, m2.cw);
+        const int ox = col + sel3(l, m0.xo, m1.xo, m2.xo);
+        const int oy = row + sel3(l, m0.yo, m1.yo, m2.yo);
+        const int cy = oy / cw, cx = ox / cw;
+        const uint32_t local = (uint32_t)((oy - cy * cw) * cw + (ox - cx * cw));
+        const uint32_t key = (s << 19) | ((uint32_t)(7 - (gs[0]->k + l)) << 16) | (0xFFFFu - local);
+        atomicMax(&keys[cy * P.ncx + cx], key);
+    }
+    wave_sync();
+}
+
+// Rows [sy, ey) of a level are cut into V equal slices (V = max(4, waves),
+// a power of two); part p takes slice p of every level, so a part never holds
+// more than 16 + 2 scored rows of any level.
+__device__ __forceinline__ void part_rows(const Geo &g, int vshift, int p, int &ra, int &rb) {
+    const int h = g.ey - g.sy;
+    const int q = (h + (1 << vshift) - 1) >> vshift;
+    ra = min(g.sy + p * q, g.ey);
+    rb = min(ra + q, g.ey);
+}
+
+// Detect levels g0..g(nl-1) of the staged sub-tile on all waves.
+__device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Geo &g2, int nl,
+                           const Params &P) {
+    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    uint16_t *list = (uint16_t *)(smem + OFF_WAVES + wave * WAVE_BYTES);
+    uint32_t *keys = (uint32_t *)(smem + OFF_KEYS);
+    const int vshift = nwaves >= 8 ? 3 : 2;
+    for (int p = wave; p < (1 << vshift); p += nwaves) {
+        int ra[3] = {0, 0, 0}, rb[3] = {0, 0, 0};
+        if (has_area(g0)) part_rows(g0, vshift, p, ra[0], rb[0]);
+        if (nl > 1 && has_area(g1)) part_rows(g1, vshift, p, ra[1], rb[1]);
+        if (nl > 2 && has_area(g2)) part_rows(g2, vshift, p, ra[2], rb[2]);
+        process_pass(smem, g0, g1, g2, ra, rb, P, list, keys);
+    }
+}
+
+// Stage level pixels [tx, tx+tw) x [ty, ty+th) into an LDS tile with 16-byte
+// loads (tx % 16 == 0, so no chunk straddles the pitch; tw <= 128).  Chunks
+// outside the plane are zero and never used as pixel values.
+__device__ void load_tile(uint8_t *tile, const uint8_t *img, int H, int P, int tx, int ty, int tw,
+                          int th) {
+    const int ch = threadIdx.x & 7;              // 8 chunk slots per row
+    const int cpr = tw >> 4;
+    if (ch >= cpr) return;
+    const int gx = tx + 16 * ch;
+    const bool col_ok = gx >= 0 && gx < P;
+    for (int r = threadIdx.x >> 3; r < th; r += blockDim.x >> 3) {
+        const int gy = ty + r;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (col_ok && gy >= 0 && gy < H) v = *(const uint4 *)(img + (size_t)gy * P + gx);
+        *(uint4 *)(tile + r * LP + 16 * ch) = v;
+    }
+}
+
+// Four pyramid pixels from two rows of eight: (a+b+c+d+2)>>2 per 2x2 block.
+__device__ __forceinline__ uint32_t halve4(uint2 a, uint2 b) {
+    const uint32_t m = 0x00FF00FFu;
+    const uint32_t s0 = (a.x & m) + ((a.x >> 8) & m) + (b.x & m) + ((b.x >> 8) & m) + 0x00020002u;
+    const uint32_t s1 = (a.y & m) + ((a.y >> 8) & m) + (b.y & m) + ((b.y >> 8) & m) + 0x00020002u;
+    return __builtin_amdgcn_perm((s1 >> 2) & m, (s0 >> 2) & m, 0x06040200u);
+}
+
+// Build an LDS level from the level above it (tile origins halve exactly;
+// tw is the destination width, a multiple of 4, at most 64).
+__device__ void halve_tile(const uint8_t *src, uint8_t *dst, int tw, int th) {
+    const int d = threadIdx.x & 15;              // 16 word slots per row
+    if (4 * d >= tw) return;
+    for (int r = threadIdx.x >> 4; r < th; r += blockDim.x >> 4) {
+        const uint8_t *s = src + (2 * r) * LP + 8 * d;
+        *(uint32_t *)(dst + r * LP + 4 * d) = halve4(*(const uint2 *)s, *(const uint2 *)(s + LP));
+    }
+}
+
+// Copy the sub-tile's own pixels of an LDS level to the pyramid plane
+// (sx % 4 == 0, ex - sx <= 32).  The last word of a row is written byte by
+// byte when it would cross the level width.
+__device__ void store_level(const uint8_t *tile, int tx, int ty, uint8_t *img, int P, int sx, int sy,
+                            int ex, int ey) {
+    const int w = threadIdx.x & 7;               // 8 word slots per row
+    const int x = sx + 4 * w;
+    if (x >= ex) return;
+    for (int y = sy + (threadIdx.x >> 3); y < ey; y += blockDim.x >> 3) {
+        const uint8_t *s = tile + (y - ty) * LP + (x - tx);
+        uint8_t *d = img + (size_t)y * P + x;
+        if (x + 4 <= ex) {
+            *(uint32_t *)d = *(const uint32_t *)s;
+        } else {
+            for (int q = 0; q < ex - x; ++q) d[q] = s[q];
+        }
+    }
+}
+
+// Zero [p, p+bytes) with 16-byte stores (p and bytes multiples of 16).
+__device__ void zero_lds(uint8_t *p, int bytes) {
+    for (int i = threadIdx.x; i < (bytes >> 4); i += blockDim.x) ((uint4 *)p)[i] = make_uint4(0, 0, 0, 0);
+}
+
+// Level-k area of the level-0 sub-tile at (sx0, sy0), clipped to the region
+// end (xr1, yr1 at level 0) and the level size.
+__device__ __forceinline__ void level_area(const fg_job &J, int k, int sx0, int sy0, int xr1,
+                                           int yr1, Geo &g) {
+    g.k = k;
+    g.W = J.w[k];
+    g.H = J.h[k];
+    g.sx = sx0 >> k;
+    g.sy = sy0 >> k;
+    g.ex = min(min((sx0 + SUB) >> k, xr1 >> k), g.W);
+    g.ey = min(min((sy0 + SUB) >> k, yr1 >> k), g.H);
+}
+
+// One level-0 sub-tile of a region: stage, detect, fold into keys.
+__device__ void process_subtile(const fg_job &J, int sx0, int sy0, int xr1, int yr1,
+                                const Params &P, uint8_t *smem) {
+    if (J.levels <= MAX_FUSED) {
+        // one load with a 4*2^(L-1) halo; levels 1.. built in LDS
+        const int H0 = 4 << (J.levels - 1);
+        const int txa = (sx0 - H0) & ~15, tya = sy0 - H0;
+        const int twa = ((min(sx0 + SUB, xr1) + H0 + 15) & ~15) - txa;
+        const int tha = min(sy0 + SUB, yr1) + H0 - tya;
+        __syncthreads();
+        load_tile(smem + T0, J.lvl[0], J.h[0], J.pitch[0], txa, tya, twa, tha);
+        zero_lds(smem + OFF_M0, OFF_KEYS - OFF_M0);
+        Geo g0, g1, g2;
+        level_area(J, 0, sx0, sy0, xr1, yr1, g0);
+        g0.tbase = T0;
+        g0.tx = txa;
+        g0.ty = tya;
+        g0.moff = OFF_M0;
+        g0.mp = M0_P;
+        set_groups(g0);
+        g1 = g0;
+        g2 = g0;
+        if (J.levels > 1) {
+            __syncthreads();
+            halve_tile(smem + T0, smem + T1, twa >> 1, tha >> 1);
+            level_area(J, 1, sx0, sy0, xr1, yr1, g1);
+            g1.tbase = T1;
+            g1.tx = txa >> 1;
+            g1.ty = tya >> 1;
+            g1.moff = OFF_M1;
+            g1.mp = M1_P;
+            set_groups(g1);
+        }
+        if (J.levels > 2) {
+            __syncthreads();
+            halve_tile(smem + T1, smem + T2, twa >> 2, tha >> 2);
+            level_area(J, 2, sx0, sy0, xr1, yr1, g2);
+            g2.tbase = T2;
+            g2.tx = txa >> 2;
+            g2.ty = tya >> 2;
+            g2.moff = OFF_M2;
+            g2.mp = M2_P;
+            set_groups(g2);
+        }
+        __syncthreads();
+        if (J.levels > 1 && has_area(g1))
+            store_level(smem + T1, g1.tx, g1.ty, J.lvl[1], J.pitch[1], g1.sx, g1.sy, g1.ex, g1.ey);
+        if (J.levels > 2 && has_area(g2))
+            store_level(smem + T2, g2.tx, g2.ty, J.lvl[2], J.pitch[2], g2.sx, g2.sy, g2.ex, g2.ey);
+        run_passes(smem, g0, g1, g2, J.levels, P);
+    } else {
+        // levels already built: one level at a time with a 4-pixel halo
+        for (int k = 0; k < J.levels; ++k) {
+            Geo g;
+            level_area(J, k, sx0, sy0, xr1, yr1, g);
+            if (!has_area(g)) continue;
+            const int tx = (g.sx - 4) & ~15, ty = g.sy - 4;
+            const int tw = ((g.ex + 4 + 15) & ~15) - tx, th = g.ey + 4 - ty;
+            __syncthreads();
+            load_tile(smem + T0, J.lvl[k], g.H, J.pitch[k], tx, ty, tw, th);
+            zero_lds(smem + OFF_M0, (M0_ROWS * M0_P * 2 + 15) & ~15);
+            __syncthreads();
+            g.tbase = T0;
+            g.tx = tx;
+            g.ty = ty;
+            g.moff = OFF_M0;
+            g.mp = M0_P;
+            set_groups(g);
+            run_passes(smem, g, g, g, 1, P);
+        }
+    }
+}
+
+__device__ void detect_region(const fg_job &J, int region, uint8_t *smem) {
     const int rxi = region % J.rx, ryi = region / J.rx;
     const int ncx = min(J.rcells, J.gw - rxi * J.rcells);
     const int ncy = min(J.rcells, J.gh - ryi * J.rcells);
-    for (int i = tid; i < ncx * ncy; i += nthr) keys[i] = 0;
-
-    for (int k = 0; k < J.levels; ++k) {
-        const int W = J.w[k], H = J.h[k], P = J.pitch[k];
-        const uint8_t *img = J.lvl[k];
-        const int cw = J.cell >> k;
-        const int x0 = rxi * J.rcells * cw, y0 = ryi * J.rcells * cw;
-        const int x1 = min(x0 + ncx * cw, W), y1 = min(y0 + ncy * cw, H);
-        for (int sy = y0; sy < y1; sy += SUB) {
-            for (int sx = x0; sx < x1; sx += SUB) {
-                const int ex = min(sx + SUB, x1), ey = min(sy + SUB, y1);
-                const int tw = ex - sx + 2 * HALO, th = ey - sy + 2 * HALO;
-                __syncthreads();
-                for (int i = tid; i < tw * th; i += nthr) {
-                    const int lx = i % tw, ly = i / tw;
-                    const int gx = sx - HALO + lx, gy = sy - HALO + ly;
-                    uint8_t v = 0;
-                    if (gx >= 0 && gx < W && gy >= 0 && gy < H) v = img[(size_t)gy * P + gx];
-                    tile[ly * TILE_P + lx] = v;
-                }
-                __syncthreads();
-                const int sw = ex - sx + 2, sh = ey - sy + 2;
-                for (int i = tid; i < sw * sh; i += nthr) {
-                    const int lx = i % sw, ly = i / sw;
-                    const int gx = sx - 1 + lx, gy = sy - 1 + ly;
-                    uint32_t s = 0;
-                    if (gx >= 3 && gx <= W - 4 && gy >= 3 && gy <= H - 4)
-                        s = fast_score(tile, lx + HALO - 1, ly + HALO - 1, J.t, J.n);
-                    sc[ly * SC_P + lx] = (uint16_t)s;
-                }
-                __syncthreads();
-                const int iw = ex - sx, ih = ey - sy;
-                for (int i = tid; i < iw * ih; i += nthr) {
-                    const int lx = i % iw, ly = i / iw;
-                    const uint16_t *c = sc + (ly + 1) * SC_P + (lx + 1);
-                    const uint32_t s = c[0];
-                    if (s == 0) continue;
-                    // earlier neighbours in row-major order must be strictly
-                    // lower; later ones lower or equal
-                    const bool keep = s > c[-SC_P - 1] && s > c[-SC_P] && s > c[-SC_P + 1] &&
-                                      s > c[-1] && s >= c[1] && s >= c[SC_P - 1] &&
-                                      s >= c[SC_P] && s >= c[SC_P + 1];
-                    if (!keep) continue;
-                    const int gx = sx + lx, gy = sy + ly;
-                    const int ox = gx - x0, oy = gy - y0;
-                    const int ci = (oy / cw) * ncx + (ox / cw);
-                    const uint32_t local = (uint32_t)((oy % cw) * cw + (ox % cw));
-                    atomicMax(&keys[ci], make_key(s, k, local));
-                }
-            }
-        }
-    }
+    uint32_t *keys = (uint32_t *)(smem + OFF_KEYS);
+    Params P;
+    P.t = J.t;
+    P.n = J.n;
+    P.kc = J.n >> 2;
+    P.k8 = J.n >> 1;
+    P.cell = J.cell;
+    P.rx0 = rxi * J.rcells * J.cell;
+    P.ry0 = ryi * J.rcells * J.cell;
+    P.ncx = ncx;
+    const int xr1 = min(P.rx0 + ncx * J.cell, J.w[0]);
+    const int yr1 = min(P.ry0 + ncy * J.cell, J.h[0]);
+    __syncthreads();   // previous region's slot writes have read the keys
+    for (int i = threadIdx.x; i < ncx * ncy; i += blockDim.x) keys[i] = 0;
+    for (int sy0 = P.ry0; sy0 < yr1; sy0 += SUB)
+        for (int sx0 = P.rx0; sx0 < xr1; sx0 += SUB) process_subtile(J, sx0, sy0, xr1, yr1, P, smem);
     __syncthreads();
-    for (int i = tid; i < ncx * ncy; i += nthr) {
+    for (int i = threadIdx.x; i < ncx * ncy; i += blockDim.x) {
         const int cx = rxi * J.rcells + i % ncx, cy = ryi * J.rcells + i / ncx;
         const uint32_t key = keys[i];
         fast_feature f;
@@ -155,19 +654,15 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
     return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
-__global__ void __launch_bounds__(1024) detect_plain_kernel(fg_job J) {
-    __shared__ uint8_t tile[TILE_W * TILE_P];
-    __shared__ uint16_t sc[SC_W * SC_P];
-    __shared__ uint32_t keys[MAX_KEYS];
-    detect_region(J, xcd_item(blockIdx.x, gridDim.x), tile, sc, keys);
+__global__ void __launch_bounds__(512) detect_plain_kernel(fg_job J) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    detect_region(J, xcd_item(blockIdx.x, gridDim.x), smem);
 }
 
-__global__ void __launch_bounds__(1024) detect_batch_kernel(const fg_job *__restrict__ jobs,
-                                                            int njobs, int total,
-                                                            unsigned *counter) {
-    __shared__ uint8_t tile[TILE_W * TILE_P];
-    __shared__ uint16_t sc[SC_W * SC_P];
-    __shared__ uint32_t keys[MAX_KEYS];
+__global__ void __launch_bounds__(512) detect_batch_kernel(const fg_job *__restrict__ jobs,
+                                                           int njobs, int total,
+                                                           unsigned *counter) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     __shared__ int s_item;
     for (;;) {
         __syncthreads();
@@ -181,8 +676,8 @@ __global__ void __launch_bounds__(1024) detect_batch_kernel(const fg_job *__rest
             if (jobs[mid].region_base <= item) lo = mid;
             else hi = mid - 1;
         }
-        const fg_job J = jobs[lo];
-        detect_region(J, item - J.region_base, tile, sc, keys);
+        const fg_job &J = jobs[lo];   // uniform: read through the scalar cache
+        detect_region(J, item - J.region_base, smem);
     }
     // The last workgroup out re-arms the queue for the next launch.
     if (threadIdx.x == 0) {
@@ -195,26 +690,34 @@ __global__ void __launch_bounds__(1024) detect_batch_kernel(const fg_job *__rest
     }
 }
 
-// Pyramid level k from level k-1 (one output pixel per thread).
+// Pyramid level k from level k-1, four output pixels per thread.
+__device__ __forceinline__ void pyr_row_words(const uint8_t *src, int sp, uint8_t *dst, int dp,
+                                              int dw, int y, int w) {
+    const int x = 4 * w;
+    const uint8_t *s0 = src + (size_t)(2 * y) * sp + 2 * x;
+    const uint8_t *s1 = s0 + sp;
+    uint8_t *d = dst + (size_t)y * dp + x;
+    if (x + 4 <= dw) {
+        *(uint32_t *)d = halve4(*(const uint2 *)s0, *(const uint2 *)s1);
+    } else {
+        for (int q = 0; q < dw - x; ++q)
+            d[q] = (uint8_t)((s0[2 * q] + s0[2 * q + 1] + s1[2 * q] + s1[2 * q + 1] + 2) >> 2);
+    }
+}
+
 __global__ void pyr_kernel(const uint8_t *__restrict__ src, int sp, uint8_t *__restrict__ dst,
                            int dw, int dh, int dp) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-    if (x >= dw || y >= dh) return;
-    const uint8_t *r0 = src + (size_t)(2 * y) * sp + 2 * x;
-    const uint8_t *r1 = r0 + sp;
-    dst[(size_t)y * dp + x] = (uint8_t)((r0[0] + r0[1] + r1[0] + r1[1] + 2) >> 2);
+    const int w = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (4 * w >= dw || y >= dh) return;
+    pyr_row_words(src, sp, dst, dp, dw, y, w);
 }
 
 __global__ void pyr_batch_kernel(const fg_job *__restrict__ jobs, int k) {
     const fg_job &J = jobs[blockIdx.z];
-    if (k >= J.levels) return;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-    const int dw = J.w[k], dh = J.h[k];
-    if (x >= dw || y >= dh) return;
-    const int sp = J.pitch[k - 1];
-    const uint8_t *r0 = J.lvl[k - 1] + (size_t)(2 * y) * sp + 2 * x;
-    const uint8_t *r1 = r0 + sp;
-    J.lvl[k][(size_t)y * J.pitch[k] + x] = (uint8_t)((r0[0] + r0[1] + r1[0] + r1[1] + 2) >> 2);
+    if (k >= J.levels || J.levels <= MAX_FUSED) return;
+    const int w = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (4 * w >= J.w[k] || y >= J.h[k]) return;
+    pyr_row_words(J.lvl[k - 1], J.pitch[k - 1], J.lvl[k], J.pitch[k], J.w[k], y, w);
 }
 
 }  // namespace
@@ -222,9 +725,15 @@ __global__ void pyr_batch_kernel(const fg_job *__restrict__ jobs, int k) {
 void fg_job_layout(fg_job &j, const fg_launch &L) {
     j.gw = (j.w[0] + j.cell - 1) / j.cell;
     j.gh = (j.h[0] + j.cell - 1) / j.cell;
+    // cells per region side: a multiple of 16/gcd(cell,16), so regions and
+    // sub-tiles start on 16-pixel boundaries
+    int g = 16;
+    while (j.cell % g) g >>= 1;
+    const int m = 16 / g;
     int rc = L.region / j.cell;
-    if (rc < 1) rc = 1;
-    if (rc > MAX_RCELLS) rc = MAX_RCELLS;
+    rc = (rc + m - 1) / m * m;
+    if (rc < m) rc = m;
+    if (rc > MAX_RCELLS) rc = MAX_RCELLS / m * m;
     j.rcells = rc;
     j.rx = (j.gw + rc - 1) / rc;
     j.ry = (j.gh + rc - 1) / rc;
@@ -232,9 +741,9 @@ void fg_job_layout(fg_job &j, const fg_launch &L) {
 
 hipError_t fg_launch_pyramid(const fg_job &j, hipStream_t s) {
     for (int k = 1; k < j.levels; ++k) {
-        dim3 grid((j.w[k] + 255) / 256, j.h[k]);
-        hipLaunchKernelGGL(pyr_kernel, grid, dim3(256), 0, s, j.lvl[k - 1], j.pitch[k - 1],
-                           j.lvl[k], j.w[k], j.h[k], j.pitch[k]);
+        dim3 grid(((j.w[k] + 3) / 4 + 63) / 64, j.h[k]);
+        hipLaunchKernelGGL(pyr_kernel, grid, dim3(64), 0, s, j.lvl[k - 1], j.pitch[k - 1], j.lvl[k],
+                           j.w[k], j.h[k], j.pitch[k]);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -242,9 +751,12 @@ hipError_t fg_launch_pyramid(const fg_job &j, hipStream_t s) {
 }
 
 hipError_t fg_launch_plain(const fg_job &j, const fg_launch &L, hipStream_t s) {
-    hipError_t e = fg_launch_pyramid(j, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(detect_plain_kernel, dim3(j.rx * j.ry), dim3(L.block), 0, s, j);
+    if (j.levels > MAX_FUSED) {
+        hipError_t e = fg_launch_pyramid(j, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(detect_plain_kernel, dim3(j.rx * j.ry), dim3(L.block),
+                       fg_smem_bytes(L.block), s, j);
     return hipGetLastError();
 }
 
@@ -252,9 +764,9 @@ hipError_t fg_launch_batch(const fg_job *jobs_dev, int njobs, int total, int max
                            int max_w1, int max_h1, unsigned *counter, const fg_launch &L,
                            hipStream_t s) {
     int mw = max_w1, mh = max_h1;
-    for (int k = 1; k < max_levels; ++k) {
-        dim3 grid((mw + 255) / 256, mh, njobs);
-        hipLaunchKernelGGL(pyr_batch_kernel, grid, dim3(256), 0, s, jobs_dev, k);
+    for (int k = 1; k < max_levels && max_levels > MAX_FUSED; ++k) {
+        dim3 grid(((mw + 3) / 4 + 63) / 64, mh, njobs);
+        hipLaunchKernelGGL(pyr_batch_kernel, grid, dim3(64), 0, s, jobs_dev, k);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         mw = (mw >> 1) > 0 ? (mw >> 1) : 1;
@@ -263,7 +775,7 @@ hipError_t fg_launch_batch(const fg_job *jobs_dev, int njobs, int total, int max
     int blocks = L.num_cu * L.blocks_per_cu;
     if (blocks > total) blocks = total;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(detect_batch_kernel, dim3(blocks), dim3(L.block), 0, s, jobs_dev, njobs,
-                       total, counter);
+    hipLaunchKernelGGL(detect_batch_kernel, dim3(blocks), dim3(L.block), fg_smem_bytes(L.block), s,
+                       jobs_dev, njobs, total, counter);
     return hipGetLastError();
 }

@@ -29,6 +29,9 @@ struct fg_launch {
     int num_cu;          // compute units on the device
 };
 
+// Dynamic LDS bytes of the detect kernels for a workgroup size.
+size_t fg_smem_bytes(int block);
+
 // Fill the derived fields of a job (grid, regions) for a launch shape.
 void fg_job_layout(fg_job &j, const fg_launch &L);
 

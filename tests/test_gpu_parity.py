@@ -108,7 +108,7 @@ def test_launch_shapes_agree(ctx):
     img = spec.make()
     want, _ = oracle.detect_grid(img, spec.width, spec.levels, spec.t, spec.n, spec.cell)
     try:
-        for region, block in ((32, 64), (64, 256), (128, 512), (256, 1024), (96, 128)):
+        for region, block in ((32, 64), (64, 256), (128, 512), (256, 128), (96, 128)):
             ctx.set_launch(region, block, 4)
             got, _ = run_plain(ctx, img, spec.width, spec.levels, spec.t, spec.n, spec.cell)
             assert np.array_equal(got, want), (region, block)
