@@ -40,20 +40,41 @@ def algorithmic_bytes(specs) -> int:
 
 
 def cpu_baseline(specs, frames, budget_s: float) -> dict:
+    """The CPU oracle, single-threaded, cycling over the batch's frames until
+    about budget_s seconds of work (a bounded sample of the same workload)."""
     import oracle
     done_px, t_total, nframes = 0, 0.0, 0
-    for s, img in zip(specs, frames):
+    while t_total < budget_s:
+        s, img = specs[nframes % len(specs)], frames[nframes % len(frames)]
         t0 = time.perf_counter()
         oracle.detect_grid(img, s.width, s.levels, s.t, s.n, s.cell)
         t_total += time.perf_counter() - t0
         done_px += s.width * s.height
         nframes += 1
-        if t_total >= budget_s:
-            break
     return {"value": round(done_px / t_total / 1e6, 3), "unit": "Mpixel/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"first {nframes} frames of the 64-frame batch, single-threaded, "
+            "sample": f"{nframes} frames of the 64-frame batch in order, single-threaded, "
                       f"{t_total:.1f} s"}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_2003_13493_amd", "csrc", "fastgrid_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the batch kernel from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "detect_batch_kernel_batch64_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def log(msg: str) -> None:
@@ -69,6 +90,10 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-latency-frames", type=int, default=300)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run device-to-device copies of this size (counter calibration)")
+    ap.add_argument("--launch", type=str, default="",
+                    help="region,block,blocks_per_cu launch shape (default: library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (frames are "
@@ -82,6 +107,8 @@ def main() -> int:
     torch.cuda.set_device(0)
     log(f"device {torch.cuda.get_device_name(0)}")
     ctx = fastgrid.Context(0)
+    if args.launch:
+        ctx.set_launch(*[int(v) for v in args.launch.split(",")])
     stream = torch.cuda.current_stream()
 
     # resident batch instances
@@ -187,7 +214,7 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(),
             "algorithmic_bytes_per_launch": bytes_per_step,
         },
         "step_ms_p50": round(float(np.percentile(step_ms, 50)), 5),
@@ -209,6 +236,14 @@ def main() -> int:
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(frames0[0], frames0[1], args.cpu_budget)
         out["cpu_baseline"]["sample"] += f"; host: {os.cpu_count()} logical CPUs"
+    if args.copy_probe_mib:
+        nbytes = args.copy_probe_mib << 20
+        src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = nbytes
     for inst in insts:
         ctx.plan_destroy(inst[4])
     ctx.close()

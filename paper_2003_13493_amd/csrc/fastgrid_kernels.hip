@@ -60,6 +60,7 @@ constexpr int MAX_KEYS = MAX_RCELLS * MAX_RCELLS;
 // Per-wave scratch: the candidate list of one part (<= 18 scored rows of each
 // level: 18*72 + 10*40 + 6*24 = 1840 pixels).
 constexpr int LIST_CAP = 1856;
+constexpr int BLIST_CAP = 164;             // groups of 8 of one segment: <= 18 * 9
 constexpr uint16_t NO_ENTRY = 0xFFFF;
 
 constexpr int OFF_M0 = TILE_BYTES;
@@ -67,7 +68,7 @@ constexpr int OFF_M1 = OFF_M0 + M0_ROWS * M0_P * 2;
 constexpr int OFF_M2 = OFF_M1 + M1_ROWS * M1_P * 2;
 constexpr int OFF_KEYS = (OFF_M2 + M2_ROWS * M2_P * 2 + 15) & ~15;
 constexpr int OFF_WAVES = OFF_KEYS + MAX_KEYS * 4;
-constexpr int WAVE_BYTES = LIST_CAP * 2;
+constexpr int WAVE_BYTES = BLIST_CAP * 4 + LIST_CAP * 2;
 static_assert(OFF_WAVES % 16 == 0 && WAVE_BYTES % 16 == 0, "aligned scratch");
 
 }  // namespace
@@ -204,38 +205,32 @@ __device__ __forceinline__ void set_groups(Geo &g) {
 
 __device__ __forceinline__ bool has_area(const Geo &g) { return g.ex > g.sx && g.ey > g.sy; }
 
-// Row and column-pair of item i of a segment with ppr pairs per row (i < 256,
-// ppr <= 9): the float quotient is exact in this range.
-__device__ __forceinline__ int item_row(int i, float inv_ppr) {
-    return (int)(((float)i + 0.5f) * inv_ppr);
-}
-
-// P1+P2 for one segment: compass test of every scored pixel (8 per lane,
-// packed 16-bit lanes), survivors kept as bits in a register, then appended
-// to the list with one wave prefix sum.  Entries are (level << 14) | (LDS
-// offset of the pixel); pixels outside the testable area (3 <= x <= W-4,
-// 3 <= y <= H-4, inside the scored ring) become NO_ENTRY.  Returns the new
-// count (wave-uniform).
+// P1+P2 for one segment: compass test of every scored pixel (8 per lane and
+// round, packed 16-bit lanes).  Groups of 8 with a survivor are compacted
+// first (ballot + mbcnt into the byte list, one 32-bit word per group:
+// LDS offset of its first pixel << 8 | survivor mask); the survivors of the
+// byte list are then expanded into the pixel list with one wave prefix sum.
+// Pixel entries are (level << 14) | (LDS offset of the pixel); pixels
+// outside the testable area (3 <= x <= W-4, 3 <= y <= H-4, inside the scored
+// ring) become NO_ENTRY.  Returns the new pixel count (wave-uniform).
 template <int K>
 __device__ int seg_collect(const uint8_t *smem, int tbase, int r_first, int nrows, int gc0, int ncolg,
                            int t, uint32_t tag, int c_lo, int c_hi, int r_lo, int r_hi,
-                           uint16_t *list, int count) {
+                           uint32_t *blist, uint16_t *list, int count) {
     const int lane = lane_id();
-    const int ppr = ncolg >> 1;                 // pairs of groups (8 pixels) per row
-    const int total = nrows * ppr;              // <= 18 * 9: at most 3 rounds of 64
-    const float inv_ppr = 1.0f / (float)ppr;
+    const int ppr = ncolg >> 1;                 // groups of 8 pixels per row
+    const int total = nrows * ppr;              // <= 18 * 9
+    const float inv_ppr = 1.0f / (float)ppr;    // (i + 0.5) * inv_ppr is exact for i < 256
     const s16x2 T1 = {(short)(t + 1), (short)(t + 1)};
-    const uint8_t *tile = smem + tbase;
-    uint32_t bits = 0;                          // 8 bits per round: bit 4h+b = pixel 2b+h
-#pragma unroll
-    for (int round = 0; round < 4; ++round) {
-        const int i = lane + 64 * round;
-        if (64 * round >= total) break;
-        uint32_t sv = 0;
+    int nb = 0;
+    for (int i0 = 0; i0 < total; i0 += 64) {
+        const int i = i0 + lane;
+        uint32_t sv = 0, off = 0;
         if (i < total) {
+            const int row = (int)(((float)i + 0.5f) * inv_ppr), pp = i - row * ppr;
+            off = (uint32_t)(tbase + (r_first + row) * LP + gc0 + 8 * pp);
             if constexpr (K > 0) {
-                const int row = item_row(i, inv_ppr), pp = i - row * ppr;
-                const uint8_t *p = tile + (r_first + row) * LP + gc0 + 8 * pp;
+                const uint8_t *p = smem + off;
                 const uint32_t D0 = *(const uint32_t *)(p - 4);
                 const uint32_t D1 = *(const uint32_t *)(p);
                 const uint32_t D2 = *(const uint32_t *)(p + 4);
@@ -256,33 +251,46 @@ __device__ int seg_collect(const uint8_t *smem, int tbase, int r_first, int nrow
                 const uint32_t r67 = as_u32(compass<K>(
                     pair(D2, D2, 0x0c030c02u), pair(N1, N1, 0x0c030c02u), pair(D3, D2, 0x0c060c05u),
                     pair(S1, S1, 0x0c030c02u), pair(D2, D1, 0x0c040c03u), T1));
-                // sign bit of each 16-bit lane = rejected; gather the 8 signs
-                uint32_t sg = ((r01 >> 15) & 0x10001u) | ((r23 >> 14) & 0x20002u) |
-                              ((r45 >> 13) & 0x40004u) | ((r67 >> 12) & 0x80008u);
+                // sign bit of each 16-bit lane = rejected; bit j <- pixel 2j,
+                // bit 4+j <- pixel 2j+1
+                const uint32_t sg = ((r01 >> 15) & 0x10001u) | ((r23 >> 14) & 0x20002u) |
+                                    ((r45 >> 13) & 0x40004u) | ((r67 >> 12) & 0x80008u);
                 sv = ~(sg | (sg >> 12)) & 0xFFu;
             } else {
                 sv = 0xFFu;
             }
         }
-        bits |= sv << (8 * round);
+        const uint64_t bal = __ballot(sv != 0);
+        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        if (sv) blist[nb + rank] = (off << 8) | sv;
+        nb += __popcll(bal);
     }
-    const int cnt = __builtin_popcount(bits);
-    const int incl = wave_scan(cnt);
-    int pos = count + incl - cnt;
-    count += __builtin_amdgcn_readlane(incl, 63);
-    while (bits) {
-        const int b = __builtin_ctz(bits);
-        bits &= bits - 1;
-        const int i = lane + 64 * (b >> 3);
-        const int row = item_row(i, inv_ppr), pp = i - row * ppr;
-        const int r = r_first + row;
-        const int q = ((b & 3) << 1) | ((b >> 2) & 1);
-        const int c = gc0 + 8 * pp + q;
-        const uint16_t e = r >= r_lo && r <= r_hi && c >= c_lo && c <= c_hi
-                               ? (uint16_t)((tag << 14) | (uint32_t)(tbase + r * LP + c))
-                               : NO_ENTRY;
-        if (pos < LIST_CAP) list[pos] = e;
-        ++pos;
+    wave_sync();
+    for (int j0 = 0; j0 < nb; j0 += 64) {
+        const int j = j0 + lane;
+        const uint32_t w = j < nb ? blist[j] : 0u;
+        uint32_t m = w & 0xFFu;
+        const int cnt = __builtin_popcount(m);
+        const int incl = wave_scan(cnt);
+        int pos = count + incl - cnt;
+        count += __builtin_amdgcn_readlane(incl, 63);
+        const int off0 = (int)(w >> 8);
+        const int rel = off0 - tbase;
+        const int r = (int)(((uint32_t)rel * 18725u) >> 21);   // rel / LP
+        const int c0 = rel - r * LP;
+        const bool row_ok = r >= r_lo && r <= r_hi;
+        while (m) {
+            const int b = __builtin_ctz(m);
+            m &= m - 1;
+            const int q = ((b & 3) << 1) | (b >> 2);
+            const int c = c0 + q;
+            const uint16_t e = row_ok && c >= c_lo && c <= c_hi
+                                   ? (uint16_t)((tag << 14) | (uint32_t)(off0 + q))
+                                   : NO_ENTRY;
+            if (pos < LIST_CAP) list[pos] = e;
+            ++pos;
+        }
     }
     return count < LIST_CAP ? count : LIST_CAP;
 }
@@ -357,8 +365,8 @@ __device__ __forceinline__ LevelMap level_map(const Geo &g, int band_row, int ba
 // when ra_l == rb_l), each scored with a 1-row ring.  P1..P5 run once over
 // the whole pass.
 __device__ void process_pass(uint8_t *smem, const Geo &g0, const Geo &g1, const Geo &g2,
-                             const int ra[3], const int rb[3], const Params &P, uint16_t *list,
-                             uint32_t *keys) {
+                             const int ra[3], const int rb[3], const Params &P, uint32_t *blist,
+                             uint16_t *list, uint32_t *keys) {
     const Geo *gs[3] = {&g0, &g1, &g2};
     int n1 = 0;
 #pragma unroll
@@ -371,7 +379,7 @@ __device__ void process_pass(uint8_t *smem, const Geo &g0, const Geo &g1, const 
         const int r_lo = max(r_first, 3 - g.ty);
         const int r_hi = min(r_first + nrows - 1, g.H - 4 - g.ty);
 #define FG_COLLECT(KK) n1 = seg_collect<KK>(smem, g.tbase, r_first, nrows, g.gc0, g.ncolg, P.t, \
-                                            (uint32_t)l, c_lo, c_hi, r_lo, r_hi, list, n1)
+                                            (uint32_t)l, c_lo, c_hi, r_lo, r_hi, blist, list, n1)
         switch (P.kc) {
             case 0: FG_COLLECT(0); break;
             case 1: FG_COLLECT(1); break;
@@ -442,7 +450,8 @@ __device__ __forceinline__ void part_rows(const Geo &g, int vshift, int p, int &
 __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Geo &g2, int nl,
                            const Params &P) {
     const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    uint16_t *list = (uint16_t *)(smem + OFF_WAVES + wave * WAVE_BYTES);
+    uint32_t *blist = (uint32_t *)(smem + OFF_WAVES + wave * WAVE_BYTES);
+    uint16_t *list = (uint16_t *)(smem + OFF_WAVES + wave * WAVE_BYTES + BLIST_CAP * 4);
     uint32_t *keys = (uint32_t *)(smem + OFF_KEYS);
     const int vshift = nwaves >= 8 ? 3 : 2;
     for (int p = wave; p < (1 << vshift); p += nwaves) {
@@ -450,7 +459,7 @@ __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Ge
         if (has_area(g0)) part_rows(g0, vshift, p, ra[0], rb[0]);
         if (nl > 1 && has_area(g1)) part_rows(g1, vshift, p, ra[1], rb[1]);
         if (nl > 2 && has_area(g2)) part_rows(g2, vshift, p, ra[2], rb[2]);
-        process_pass(smem, g0, g1, g2, ra, rb, P, list, keys);
+        process_pass(smem, g0, g1, g2, ra, rb, P, blist, list, keys);
     }
 }
 
@@ -464,11 +473,25 @@ __device__ void load_tile(uint8_t *tile, const uint8_t *img, int H, int P, int t
     if (ch >= cpr) return;
     const int gx = tx + 16 * ch;
     const bool col_ok = gx >= 0 && gx < P;
-    for (int r = threadIdx.x >> 3; r < th; r += blockDim.x >> 3) {
+    const int r0 = threadIdx.x >> 3, dr = blockDim.x >> 3;
+    // all loads in flight before the first store (th <= 4 * dr for block >= 256)
+    uint4 v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r = r0 + j * dr, gy = ty + r;
+        v[j] = make_uint4(0, 0, 0, 0);
+        if (r < th && col_ok && gy >= 0 && gy < H) v[j] = *(const uint4 *)(img + (size_t)gy * P + gx);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r = r0 + j * dr;
+        if (r < th) *(uint4 *)(tile + r * LP + 16 * ch) = v[j];
+    }
+    for (int r = r0 + 4 * dr; r < th; r += dr) {   // small workgroups only
         const int gy = ty + r;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (col_ok && gy >= 0 && gy < H) v = *(const uint4 *)(img + (size_t)gy * P + gx);
-        *(uint4 *)(tile + r * LP + 16 * ch) = v;
+        uint4 w = make_uint4(0, 0, 0, 0);
+        if (col_ok && gy >= 0 && gy < H) w = *(const uint4 *)(img + (size_t)gy * P + gx);
+        *(uint4 *)(tile + r * LP + 16 * ch) = w;
     }
 }
 

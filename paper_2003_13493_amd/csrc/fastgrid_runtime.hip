@@ -215,7 +215,7 @@ FG_API int fast_ctx_create(int hip_device, fast_ctx **out) {
     c->launch.num_cu = cus;
     c->launch.region = 64;
     c->launch.block = 256;
-    c->launch.blocks_per_cu = 4;
+    c->launch.blocks_per_cu = 3;
     for (int i = 0; i < TICKET_RING; ++i) {
         hipError_t e = hipEventCreateWithFlags(&c->events[i], hipEventDisableTiming);
         if (e != hipSuccess) {

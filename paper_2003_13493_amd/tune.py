@@ -1,0 +1,131 @@
+"""Launch-shape autotuner for the batched detector.
+
+Candidates are (region, block, persistent blocks per CU): the side of the
+level-0 region a workgroup owns, the workgroup size (waves per region) and the
+occupancy target of the persistent kernel.  Every candidate is first run once
+and its output compared bit for bit with the output of the reference shape on
+the same frames; only candidates that match are timed.  Timing is the median
+of graph replays measured with device events.
+
+Results are cached as JSON keyed by the workload signature (frame sizes,
+levels, cells), so a serving process can load the tuned shape at start-up.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import numpy as np
+
+from . import fastgrid
+
+DEFAULT_SHAPE = (64, 256, 3)
+CANDIDATES = [
+    (64, 256, 2), (64, 256, 3), (64, 256, 4), (64, 256, 8),
+    (64, 512, 1), (64, 512, 2), (64, 512, 4),
+    (64, 128, 4), (64, 128, 8), (128, 256, 3), (128, 512, 2), (32, 256, 4),
+]
+
+
+def signature(specs) -> str:
+    """A stable key for a workload: the multiset of (W, H, levels, cell)."""
+    keys = sorted({(s.width, s.height, s.levels, s.cell) for s in specs})
+    return ";".join(f"{w}x{h}L{l}c{c}" for w, h, l, c in keys)
+
+
+class _Resident:
+    """Device-resident frames and outputs of one workload."""
+
+    def __init__(self, specs, frames):
+        self.specs = specs
+        self.pyrs, self.grids = [], []
+        for s, img in zip(specs, frames):
+            p = fastgrid.Pyramid(s.width, s.height, s.levels)
+            p.upload(img)
+            self.pyrs.append(p)
+            self.grids.append(fastgrid.Grid(s.width, s.height, s.cell))
+        self.jobs = fastgrid.Context.make_jobs(
+            (p, s.t, s.n, s.cell, g) for p, s, g in zip(self.pyrs, specs, self.grids))
+
+    def outputs(self):
+        return [g.fetch().copy() for g in self.grids]
+
+
+def _time_plan(ctx, res, reps: int, warmup: int) -> float:
+    import torch
+    pid = ctx.plan_create(res.jobs)
+    try:
+        stream = torch.cuda.current_stream()
+        for _ in range(warmup):
+            ctx.plan_launch(pid, stream)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record(stream)
+        for i in range(reps):
+            ctx.plan_launch(pid, stream)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+        return float(np.median(ms))
+    finally:
+        ctx.plan_destroy(pid)
+
+
+def tune(ctx: fastgrid.Context, specs, frames, candidates=None, reps: int = 30,
+         warmup: int = 5, log=None) -> dict:
+    """Try every candidate shape on the workload; return the table and the best.
+
+    A candidate whose output differs from the reference shape's is rejected
+    (reported with ``"exact": False``) and never timed."""
+    import torch
+    candidates = list(candidates or CANDIDATES)
+    res = _Resident(specs, frames)
+    ctx.set_launch(*DEFAULT_SHAPE)
+    tk = ctx.submit(res.jobs)
+    ctx.wait(tk)
+    reference = res.outputs()
+    table = []
+    for shape in candidates:
+        try:
+            ctx.set_launch(*shape)
+        except fastgrid.FastError as e:
+            table.append({"shape": list(shape), "exact": False, "error": str(e)})
+            continue
+        for g in res.grids:
+            g.tensor.fill_(0xA5)
+        torch.cuda.synchronize()
+        tk = ctx.submit(res.jobs)
+        ctx.wait(tk)
+        exact = all(np.array_equal(a, b) for a, b in zip(res.outputs(), reference))
+        row = {"shape": list(shape), "exact": exact}
+        if exact:
+            row["ms"] = _time_plan(ctx, res, reps, warmup)
+        table.append(row)
+        if log:
+            log(f"tune {shape}: exact={exact} ms={row.get('ms')}")
+    timed = [r for r in table if r.get("exact") and "ms" in r]
+    best = min(timed, key=lambda r: r["ms"]) if timed else {"shape": list(DEFAULT_SHAPE)}
+    ctx.set_launch(*best["shape"])
+    return {"signature": signature(specs), "best": best["shape"], "table": table,
+            "time": time.strftime("%Y-%m-%d %H:%M:%S")}
+
+
+def save(result: dict, path: str) -> None:
+    cache = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            cache = json.load(f)
+    cache[result["signature"]] = result
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1)
+
+
+def load_best(path: str, specs):
+    """The cached best shape for this workload, or None."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        cache = json.load(f)
+    hit = cache.get(signature(specs))
+    return tuple(hit["best"]) if hit else None

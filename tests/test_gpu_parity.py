@@ -113,7 +113,7 @@ def test_launch_shapes_agree(ctx):
             got, _ = run_plain(ctx, img, spec.width, spec.levels, spec.t, spec.n, spec.cell)
             assert np.array_equal(got, want), (region, block)
     finally:
-        ctx.set_launch(64, 256, 4)
+        ctx.set_launch(64, 256, 3)
 
 
 def test_pyr_build_entry_point(ctx):
