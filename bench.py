@@ -77,6 +77,37 @@ def measured_traffic():
     return rec.get("hbm_bytes_per_launch")
 
 
+def serving(ctx, seconds: float) -> dict:
+    """32 Poisson camera streams through the continuous-batching server, then
+    the same arrivals served one frame per launch."""
+    from paper_2003_13493_amd import serve, synth
+    specs = synth.streams32()
+    res = {"workload": "32 camera streams: 640x480, 752x480, 1920x1080, 4096x2160 (8 each), "
+                       "3-5 levels, per-stream t/N/cell, Poisson 100-1000 frames/s each, "
+                       f"{seconds} s of arrivals per mode; results copied to pinned host; "
+                       "the _x4 entries run every stream at 4x its rate"}
+    srv = serve.Server(ctx, specs, pool_frames=4, slots_per_stream=4, max_batch=64, inflight=4)
+    res["offered_mpixel_s"] = round(sum(s.width * s.height * s.rate_fps for s in specs) / 1e6, 1)
+    for scale in (1.0, 4.0):
+        for mode, batched in (("batched", True), ("plain", False)):
+            srv.run(0.2, seed=99, batched=batched, rate_scale=scale)          # warm-up
+            st = srv.run(seconds, seed=17, batched=batched, rate_scale=scale)
+            st.pop("requests")
+            for k in ("mpixel_s", "wall_s", "mean_batch"):
+                st[k] = round(st[k], 3)
+            st["latency_ms"] = {k: round(v, 4) for k, v in st["latency_ms"].items()}
+            st["latency_ms_by_resolution"] = {
+                r: {k: round(v, 4) for k, v in d.items()}
+                for r, d in st["latency_ms_by_resolution"].items()}
+            key = mode if scale == 1.0 else f"{mode}_x{scale:g}"
+            res[key] = st
+            log(f"serving {key}: {st['frames']} frames in {st['wall_s']} s, {st['mpixel_s']} Mpx/s, "
+                f"mean batch {st['mean_batch']}, p50 {st['latency_ms']['p50']} ms "
+                f"p99 {st['latency_ms']['p99']} ms")
+    srv.close()
+    return res
+
+
 def log(msg: str) -> None:
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
@@ -92,6 +123,8 @@ def main() -> int:
     ap.add_argument("--plain-latency-frames", type=int, default=300)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run device-to-device copies of this size (counter calibration)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="seconds of Poisson arrivals per serving mode (0 skips serving)")
     ap.add_argument("--launch", type=str, default="",
                     help="region,block,blocks_per_cu launch shape (default: library default)")
     args = ap.parse_args()
@@ -135,22 +168,46 @@ def main() -> int:
     px_per_step = sum(s.width * s.height for s in specs0)
     bytes_per_step = algorithmic_bytes(specs0)
 
-    # ---- batched (graph replay of the persistent launch)
+    # ---- batched: one persistent launch per step from a resident job table
     for i in range(args.warmup):
-        ctx.plan_launch(insts[i % len(insts)][4], stream)
+        ctx.plan_launch(insts[i % len(insts)][4], stream, ticket=False)
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t_wall0 = time.perf_counter()
-    ev[0].record(stream)
+    e0.record(stream)
     for i in range(args.steps):
-        ctx.plan_launch(insts[i % len(insts)][4], stream)
-        ev[i + 1].record(stream)
+        ctx.plan_launch(insts[i % len(insts)][4], stream, ticket=False)
+    e1.record(stream)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall0
-    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
-    total_ms = ev[0].elapsed_time(ev[-1])
+    total_ms = e0.elapsed_time(e1)
     ms_per_step = total_ms / args.steps
     value = px_per_step * args.steps / (total_ms / 1e3) / 1e6
+
+    # step-time distribution: the same launches with an event after each one
+    # (each event adds a few microseconds, so this pass is not the headline)
+    nd = min(args.steps, 100)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nd + 1)]
+    ev[0].record(stream)
+    for i in range(nd):
+        ctx.plan_launch(insts[i % len(insts)][4], stream, ticket=False)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(nd)])
+
+    # the same resident batches replayed as captured HIP graphs
+    gplans = [ctx.plan_create(inst[3], graph=True) for inst in insts]
+    for i in range(args.warmup):
+        ctx.plan_launch(gplans[i % len(gplans)], stream, ticket=False)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(args.steps):
+        ctx.plan_launch(gplans[i % len(gplans)], stream, ticket=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / args.steps
+    for g in gplans:
+        ctx.plan_destroy(g)
 
     log(f"batched: {ms_per_step:.4f} ms/step")
     # ---- plain path over the same 64 frames: one launch per frame
@@ -217,6 +274,7 @@ def main() -> int:
             "traffic": measured_traffic(),
             "algorithmic_bytes_per_launch": bytes_per_step,
         },
+        "graph_replay_ms_per_step": round(graph_ms, 5),
         "step_ms_p50": round(float(np.percentile(step_ms, 50)), 5),
         "step_ms_p99": round(float(np.percentile(step_ms, 99)), 5),
         "plain": {
@@ -233,6 +291,8 @@ def main() -> int:
         "wall_s_timed": round(t_wall, 3),
     }
     log(f"plain: {plain_ms:.4f} ms per 64 frames; latency p50 {np.percentile(lat, 50):.4f} ms")
+    if args.serve_seconds > 0:
+        out["serving"] = serving(ctx, args.serve_seconds)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(frames0[0], frames0[1], args.cpu_budget)
         out["cpu_baseline"]["sample"] += f"; host: {os.cpu_count()} logical CPUs"

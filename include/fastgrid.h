@@ -152,12 +152,21 @@ int fast_poll(fast_ctx *ctx, uint64_t ticket);
 int fast_wait(fast_ctx *ctx, uint64_t ticket, int timeout_ms);
 
 /* A resident batch: the job table is uploaded once into context-owned device
- * memory and the launch sequence is captured into a HIP graph; each replay
- * re-runs the whole batch on the frames currently in the jobs' planes.
- * *plan_id receives a handle (>= 0).  Errors as for fast_submit, FAST_ENOMEM. */
-int fast_plan_create(fast_ctx *ctx, const fast_job *jobs, int njobs, int *plan_id);
+ * memory; each launch re-runs the whole batch on the frames currently in the
+ * jobs' planes.  flags = 0: every launch enqueues the kernels directly from the
+ * resident table, with the context's launch shape at that moment.
+ * flags = FAST_PLAN_GRAPH: the launch sequence (with the launch shape current
+ * at creation) is captured into a HIP graph, and every launch replays it.
+ * *plan_id receives a handle (>= 0).  Launches of one plan share its
+ * work-queue counter, so they must not run concurrently (enqueue them on one
+ * stream).  Errors as for fast_submit, FAST_EINVAL for unknown flags,
+ * FAST_ENOMEM. */
+#define FAST_PLAN_GRAPH 1
+int fast_plan_create(fast_ctx *ctx, const fast_job *jobs, int njobs, int flags, int *plan_id);
 
-/* Replay a resident batch on `stream`; *ticket as for fast_submit. */
+/* Launch a resident batch on `stream`.  If ticket is non-NULL, a completion
+ * event is recorded and *ticket works as for fast_submit; with ticket = NULL
+ * no event is recorded (the caller synchronises on the stream itself). */
 int fast_plan_launch(fast_ctx *ctx, int plan_id, void *stream, uint64_t *ticket);
 
 /* Release a resident batch (after its launches complete). */

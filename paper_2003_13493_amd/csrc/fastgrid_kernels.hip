@@ -68,7 +68,7 @@ constexpr int OFF_M1 = OFF_M0 + M0_ROWS * M0_P * 2;
 constexpr int OFF_M2 = OFF_M1 + M1_ROWS * M1_P * 2;
 constexpr int OFF_KEYS = (OFF_M2 + M2_ROWS * M2_P * 2 + 15) & ~15;
 constexpr int OFF_WAVES = OFF_KEYS + MAX_KEYS * 4;
-constexpr int WAVE_BYTES = BLIST_CAP * 4 + LIST_CAP * 2;
+constexpr int WAVE_BYTES = BLIST_CAP * 4 + (LIST_CAP + 64) * 2;   // + one spare slot per lane
 static_assert(OFF_WAVES % 16 == 0 && WAVE_BYTES % 16 == 0, "aligned scratch");
 
 }  // namespace
@@ -78,6 +78,22 @@ size_t fg_smem_bytes(int block) { return (size_t)OFF_WAVES + (size_t)(block / 64
 namespace {
 
 typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Image planes and outputs reach the kernels as generic pointers inside job
+// structs.  Accessing them through global-address-space pointers makes the
+// compiler emit global (not flat) loads and stores, which are counted by
+// vmcnt only: outstanding HBM traffic then never holds up an LDS wait.
+#define GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ T gload(const void *p) {
+    return *(const GLOBAL T *)p;
+}
+template <class T>
+__device__ __forceinline__ void gstore(void *p, T v) {
+    *(GLOBAL T *)p = v;
+}
 
 __device__ __forceinline__ s16x2 as_s16x2(uint32_t v) { return __builtin_bit_cast(s16x2, v); }
 __device__ __forceinline__ uint32_t as_u32(s16x2 v) { return __builtin_bit_cast(uint32_t, v); }
@@ -270,26 +286,30 @@ __device__ int seg_collect(const uint8_t *smem, int tbase, int r_first, int nrow
     for (int j0 = 0; j0 < nb; j0 += 64) {
         const int j = j0 + lane;
         const uint32_t w = j < nb ? blist[j] : 0u;
-        uint32_t m = w & 0xFFu;
+        const uint32_t m = w & 0xFFu;
         const int cnt = __builtin_popcount(m);
         const int incl = wave_scan(cnt);
-        int pos = count + incl - cnt;
+        const int pos = count + incl - cnt;
         count += __builtin_amdgcn_readlane(incl, 63);
         const int off0 = (int)(w >> 8);
         const int rel = off0 - tbase;
         const int r = (int)(((uint32_t)rel * 18725u) >> 21);   // rel / LP
         const int c0 = rel - r * LP;
         const bool row_ok = r >= r_lo && r <= r_hi;
-        while (m) {
-            const int b = __builtin_ctz(m);
-            m &= m - 1;
+        const uint32_t base = (tag << 14) | (uint32_t)off0;
+        // Bit b of the mask is pixel q(b) of the group (see the packing
+        // above); a set bit is written at pos + (set bits below it).  Clear
+        // bits write to the lane's own slot past the list, so the loop has
+        // no branches.
+        const int spare = LIST_CAP + lane;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
             const int q = ((b & 3) << 1) | (b >> 2);
+            int at = pos + __builtin_popcount(m & ((1u << b) - 1u));
+            at = ((m >> b) & 1u) && at < LIST_CAP ? at : spare;
             const int c = c0 + q;
-            const uint16_t e = row_ok && c >= c_lo && c <= c_hi
-                                   ? (uint16_t)((tag << 14) | (uint32_t)(off0 + q))
-                                   : NO_ENTRY;
-            if (pos < LIST_CAP) list[pos] = e;
-            ++pos;
+            const bool ok = row_ok && c >= c_lo && c <= c_hi;
+            list[at] = ok ? (uint16_t)(base + (uint32_t)q) : NO_ENTRY;
         }
     }
     return count < LIST_CAP ? count : LIST_CAP;
@@ -465,33 +485,53 @@ __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Ge
 
 // Stage level pixels [tx, tx+tw) x [ty, ty+th) into an LDS tile with 16-byte
 // loads (tx % 16 == 0, so no chunk straddles the pitch; tw <= 128).  Chunks
-// outside the plane are zero and never used as pixel values.
-__device__ void load_tile(uint8_t *tile, const uint8_t *img, int H, int P, int tx, int ty, int tw,
-                          int th) {
-    const int ch = threadIdx.x & 7;              // 8 chunk slots per row
-    const int cpr = tw >> 4;
-    if (ch >= cpr) return;
+// outside the plane are zero and never used as pixel values.  Thread i owns
+// chunk column i % 8 of rows i/8 + j * (block/8); the first four of its rows
+// are loaded into registers (TileRegs) before any store.
+struct TileRegs {
+    u32x4 v[4];
+};
+
+__device__ __forceinline__ void tile_issue(TileRegs &R, const uint8_t *img, int H, int P, int tx, int ty,
+                                           int tw, int th) {
+    const int ch = threadIdx.x & 7;
     const int gx = tx + 16 * ch;
-    const bool col_ok = gx >= 0 && gx < P;
+    const bool col_ok = ch < (tw >> 4) && gx >= 0 && gx < P;
     const int r0 = threadIdx.x >> 3, dr = blockDim.x >> 3;
-    // all loads in flight before the first store (th <= 4 * dr for block >= 256)
-    uint4 v[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int r = r0 + j * dr, gy = ty + r;
-        v[j] = make_uint4(0, 0, 0, 0);
-        if (r < th && col_ok && gy >= 0 && gy < H) v[j] = *(const uint4 *)(img + (size_t)gy * P + gx);
+        R.v[j] = u32x4{0u, 0u, 0u, 0u};
+        if (r < th && col_ok && gy >= 0 && gy < H) R.v[j] = gload<u32x4>(img + (size_t)gy * P + gx);
     }
+}
+
+__device__ __forceinline__ void tile_commit(uint8_t *tile, const TileRegs &R, int tw, int th) {
+    const int ch = threadIdx.x & 7;
+    if (ch >= (tw >> 4)) return;
+    const int r0 = threadIdx.x >> 3, dr = blockDim.x >> 3;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int r = r0 + j * dr;
-        if (r < th) *(uint4 *)(tile + r * LP + 16 * ch) = v[j];
+        if (r < th) *(u32x4 *)(tile + r * LP + 16 * ch) = R.v[j];
     }
-    for (int r = r0 + 4 * dr; r < th; r += dr) {   // small workgroups only
+}
+
+__device__ void load_tile(uint8_t *tile, const uint8_t *img, int H, int P, int tx, int ty, int tw,
+                          int th) {
+    TileRegs R;
+    tile_issue(R, img, H, P, tx, ty, tw, th);
+    tile_commit(tile, R, tw, th);
+    const int ch = threadIdx.x & 7;
+    if (ch >= (tw >> 4)) return;
+    const int gx = tx + 16 * ch;
+    const bool col_ok = gx >= 0 && gx < P;
+    const int dr = blockDim.x >> 3;
+    for (int r = (threadIdx.x >> 3) + 4 * dr; r < th; r += dr) {   // small workgroups only
         const int gy = ty + r;
-        uint4 w = make_uint4(0, 0, 0, 0);
-        if (col_ok && gy >= 0 && gy < H) w = *(const uint4 *)(img + (size_t)gy * P + gx);
-        *(uint4 *)(tile + r * LP + 16 * ch) = w;
+        u32x4 w = u32x4{0u, 0u, 0u, 0u};
+        if (col_ok && gy >= 0 && gy < H) w = gload<u32x4>(img + (size_t)gy * P + gx);
+        *(u32x4 *)(tile + r * LP + 16 * ch) = w;
     }
 }
 
@@ -526,9 +566,9 @@ __device__ void store_level(const uint8_t *tile, int tx, int ty, uint8_t *img, i
         const uint8_t *s = tile + (y - ty) * LP + (x - tx);
         uint8_t *d = img + (size_t)y * P + x;
         if (x + 4 <= ex) {
-            *(uint32_t *)d = *(const uint32_t *)s;
+            gstore<uint32_t>(d, *(const uint32_t *)s);
         } else {
-            for (int q = 0; q < ex - x; ++q) d[q] = s[q];
+            for (int q = 0; q < ex - x; ++q) gstore<uint8_t>(d + q, s[q]);
         }
     }
 }
@@ -551,55 +591,75 @@ __device__ __forceinline__ void level_area(const fg_job &J, int k, int sx0, int 
     g.ey = min(min((sy0 + SUB) >> k, yr1 >> k), g.H);
 }
 
+// Level-0 tile of a fused sub-tile: the sub-tile plus a 4*2^(L-1) halo, with
+// the left edge rounded down to 16 pixels.
+struct Stage {
+    int tx, ty, tw, th;
+};
+
+__device__ __forceinline__ Stage fused_stage(const fg_job &J, int sx0, int sy0, int xr1, int yr1) {
+    const int H0 = 4 << (J.levels - 1);
+    Stage st;
+    st.tx = (sx0 - H0) & ~15;
+    st.ty = sy0 - H0;
+    st.tw = ((min(sx0 + SUB, xr1) + H0 + 15) & ~15) - st.tx;
+    st.th = min(sy0 + SUB, yr1) + H0 - st.ty;
+    return st;
+}
+
+// With level 0 of a fused sub-tile in LDS: build levels 1.. in LDS, describe
+// every level, and write levels 1.. of the sub-tile to their planes.
+__device__ void build_fused(const fg_job &J, int sx0, int sy0, int xr1, int yr1, const Stage &st,
+                            uint8_t *smem, Geo &g0, Geo &g1, Geo &g2) {
+    level_area(J, 0, sx0, sy0, xr1, yr1, g0);
+    g0.tbase = T0;
+    g0.tx = st.tx;
+    g0.ty = st.ty;
+    g0.moff = OFF_M0;
+    g0.mp = M0_P;
+    set_groups(g0);
+    g1 = g0;
+    g2 = g0;
+    if (J.levels > 1) {
+        __syncthreads();
+        halve_tile(smem + T0, smem + T1, st.tw >> 1, st.th >> 1);
+        level_area(J, 1, sx0, sy0, xr1, yr1, g1);
+        g1.tbase = T1;
+        g1.tx = st.tx >> 1;
+        g1.ty = st.ty >> 1;
+        g1.moff = OFF_M1;
+        g1.mp = M1_P;
+        set_groups(g1);
+    }
+    if (J.levels > 2) {
+        __syncthreads();
+        halve_tile(smem + T1, smem + T2, st.tw >> 2, st.th >> 2);
+        level_area(J, 2, sx0, sy0, xr1, yr1, g2);
+        g2.tbase = T2;
+        g2.tx = st.tx >> 2;
+        g2.ty = st.ty >> 2;
+        g2.moff = OFF_M2;
+        g2.mp = M2_P;
+        set_groups(g2);
+    }
+    __syncthreads();
+    if (J.levels > 1 && has_area(g1))
+        store_level(smem + T1, g1.tx, g1.ty, J.lvl[1], J.pitch[1], g1.sx, g1.sy, g1.ex, g1.ey);
+    if (J.levels > 2 && has_area(g2))
+        store_level(smem + T2, g2.tx, g2.ty, J.lvl[2], J.pitch[2], g2.sx, g2.sy, g2.ex, g2.ey);
+}
+
 // One level-0 sub-tile of a region: stage, detect, fold into keys.
 __device__ void process_subtile(const fg_job &J, int sx0, int sy0, int xr1, int yr1,
                                 const Params &P, uint8_t *smem) {
     if (J.levels <= MAX_FUSED) {
         // one load with a 4*2^(L-1) halo; levels 1.. built in LDS
-        const int H0 = 4 << (J.levels - 1);
-        const int txa = (sx0 - H0) & ~15, tya = sy0 - H0;
-        const int twa = ((min(sx0 + SUB, xr1) + H0 + 15) & ~15) - txa;
-        const int tha = min(sy0 + SUB, yr1) + H0 - tya;
+        const Stage st = fused_stage(J, sx0, sy0, xr1, yr1);
         __syncthreads();
-        load_tile(smem + T0, J.lvl[0], J.h[0], J.pitch[0], txa, tya, twa, tha);
+        load_tile(smem + T0, J.lvl[0], J.h[0], J.pitch[0], st.tx, st.ty, st.tw, st.th);
         zero_lds(smem + OFF_M0, OFF_KEYS - OFF_M0);
         Geo g0, g1, g2;
-        level_area(J, 0, sx0, sy0, xr1, yr1, g0);
-        g0.tbase = T0;
-        g0.tx = txa;
-        g0.ty = tya;
-        g0.moff = OFF_M0;
-        g0.mp = M0_P;
-        set_groups(g0);
-        g1 = g0;
-        g2 = g0;
-        if (J.levels > 1) {
-            __syncthreads();
-            halve_tile(smem + T0, smem + T1, twa >> 1, tha >> 1);
-            level_area(J, 1, sx0, sy0, xr1, yr1, g1);
-            g1.tbase = T1;
-            g1.tx = txa >> 1;
-            g1.ty = tya >> 1;
-            g1.moff = OFF_M1;
-            g1.mp = M1_P;
-            set_groups(g1);
-        }
-        if (J.levels > 2) {
-            __syncthreads();
-            halve_tile(smem + T1, smem + T2, twa >> 2, tha >> 2);
-            level_area(J, 2, sx0, sy0, xr1, yr1, g2);
-            g2.tbase = T2;
-            g2.tx = txa >> 2;
-            g2.ty = tya >> 2;
-            g2.moff = OFF_M2;
-            g2.mp = M2_P;
-            set_groups(g2);
-        }
-        __syncthreads();
-        if (J.levels > 1 && has_area(g1))
-            store_level(smem + T1, g1.tx, g1.ty, J.lvl[1], J.pitch[1], g1.sx, g1.sy, g1.ex, g1.ey);
-        if (J.levels > 2 && has_area(g2))
-            store_level(smem + T2, g2.tx, g2.ty, J.lvl[2], J.pitch[2], g2.sx, g2.sy, g2.ex, g2.ey);
+        build_fused(J, sx0, sy0, xr1, yr1, st, smem, g0, g1, g2);
         run_passes(smem, g0, g1, g2, J.levels, P);
     } else {
         // levels already built: one level at a time with a 4-pixel halo
@@ -624,48 +684,81 @@ __device__ void process_subtile(const fg_job &J, int sx0, int sy0, int xr1, int 
     }
 }
 
-__device__ void detect_region(const fg_job &J, int region, uint8_t *smem) {
-    const int rxi = region % J.rx, ryi = region / J.rx;
-    const int ncx = min(J.rcells, J.gw - rxi * J.rcells);
-    const int ncy = min(J.rcells, J.gh - ryi * J.rcells);
-    uint32_t *keys = (uint32_t *)(smem + OFF_KEYS);
+// A region of a job: its cells and its level-0 extent.
+struct Region {
+    int rxi, ryi;        // region column and row
+    int ncx, ncy;        // cells across and down (clipped at the grid edge)
+    int xr1, yr1;        // level-0 end of the region (clipped at the image)
     Params P;
-    P.t = J.t;
-    P.n = J.n;
-    P.kc = J.n >> 2;
-    P.k8 = J.n >> 1;
-    P.cell = J.cell;
-    P.rx0 = rxi * J.rcells * J.cell;
-    P.ry0 = ryi * J.rcells * J.cell;
-    P.ncx = ncx;
-    const int xr1 = min(P.rx0 + ncx * J.cell, J.w[0]);
-    const int yr1 = min(P.ry0 + ncy * J.cell, J.h[0]);
-    __syncthreads();   // previous region's slot writes have read the keys
-    for (int i = threadIdx.x; i < ncx * ncy; i += blockDim.x) keys[i] = 0;
-    for (int sy0 = P.ry0; sy0 < yr1; sy0 += SUB)
-        for (int sx0 = P.rx0; sx0 < xr1; sx0 += SUB) process_subtile(J, sx0, sy0, xr1, yr1, P, smem);
-    __syncthreads();
-    for (int i = threadIdx.x; i < ncx * ncy; i += blockDim.x) {
-        const int cx = rxi * J.rcells + i % ncx, cy = ryi * J.rcells + i / ncx;
+};
+
+__device__ __forceinline__ Region region_of(const fg_job &J, int region) {
+    Region R;
+    R.rxi = region % J.rx;
+    R.ryi = region / J.rx;
+    R.ncx = min(J.rcells, J.gw - R.rxi * J.rcells);
+    R.ncy = min(J.rcells, J.gh - R.ryi * J.rcells);
+    R.P.t = J.t;
+    R.P.n = J.n;
+    R.P.kc = J.n >> 2;
+    R.P.k8 = J.n >> 1;
+    R.P.cell = J.cell;
+    R.P.rx0 = R.rxi * J.rcells * J.cell;
+    R.P.ry0 = R.ryi * J.rcells * J.cell;
+    R.P.ncx = R.ncx;
+    R.xr1 = min(R.P.rx0 + R.ncx * J.cell, J.w[0]);
+    R.yr1 = min(R.P.ry0 + R.ncy * J.cell, J.h[0]);
+    return R;
+}
+
+__device__ __forceinline__ void keys_clear(uint32_t *keys, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) keys[i] = 0;
+}
+
+// Decode the region's cell keys into output slots.
+__device__ void keys_write(const fg_job &J, const Region &R, const uint32_t *keys) {
+    for (int i = threadIdx.x; i < R.ncx * R.ncy; i += blockDim.x) {
+        const int cx = R.rxi * J.rcells + i % R.ncx, cy = R.ryi * J.rcells + i / R.ncx;
         const uint32_t key = keys[i];
-        fast_feature f;
+        // fast_feature {x, y, score, level, reserved} as one little-endian word
+        uint64_t f;
         if (key == 0) {
-            f.x = 0xFFFF;
-            f.y = 0xFFFF;
-            f.score = 0;
-            f.level = 0xFF;
+            f = 0x00FF0000FFFFFFFFull;
         } else {
             const int level = 7 - (int)((key >> 16) & 7u);
             const uint32_t local = 0xFFFFu - (key & 0xFFFFu);
             const int cw = J.cell >> level;
-            f.x = (uint16_t)(((cx * J.cell) >> level) + (int)(local % (uint32_t)cw));
-            f.y = (uint16_t)(((cy * J.cell) >> level) + (int)(local / (uint32_t)cw));
-            f.score = (uint16_t)(key >> 19);
-            f.level = (uint8_t)level;
+            const uint32_t x = (uint32_t)(((cx * J.cell) >> level) + (int)(local % (uint32_t)cw));
+            const uint32_t y = (uint32_t)(((cy * J.cell) >> level) + (int)(local / (uint32_t)cw));
+            f = (uint64_t)(x | (y << 16)) | ((uint64_t)(key >> 19) << 32) | ((uint64_t)level << 48);
         }
-        f.reserved = 0;
-        J.out[(size_t)cy * J.gw + cx] = f;
+        gstore<uint64_t>(J.out + (size_t)cy * J.gw + cx, f);
     }
+}
+
+__device__ void detect_region(const fg_job &J, int region, uint8_t *smem) {
+    const Region R = region_of(J, region);
+    uint32_t *keys = (uint32_t *)(smem + OFF_KEYS);
+    __syncthreads();   // previous region's slot writes have read the keys
+    keys_clear(keys, R.ncx * R.ncy);
+    for (int sy0 = R.P.ry0; sy0 < R.yr1; sy0 += SUB)
+        for (int sx0 = R.P.rx0; sx0 < R.xr1; sx0 += SUB)
+            process_subtile(J, sx0, sy0, R.xr1, R.yr1, R.P, smem);
+    __syncthreads();
+    keys_write(J, R, keys);
+}
+
+// A region is one fused sub-tile when its pyramid is built in LDS and it is
+// at most one sub-tile wide and tall.
+__device__ __forceinline__ bool single_fused(const fg_job &J) {
+    return J.levels <= MAX_FUSED && J.rcells * J.cell <= SUB;
+}
+
+// Issue the level-0 tile loads of a single-fused-sub-tile region.
+__device__ __forceinline__ void region_prefetch(const fg_job &J, int region, TileRegs &T) {
+    const Region R = region_of(J, region);
+    const Stage st = fused_stage(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1);
+    tile_issue(T, J.lvl[0], J.h[0], J.pitch[0], st.tx, st.ty, st.tw, st.th);
 }
 
 // Bijective block -> item map that gives each XCD (blocks are dealt to the 8
@@ -682,27 +775,79 @@ __global__ void __launch_bounds__(512) detect_plain_kernel(fg_job J) {
     detect_region(J, xcd_item(blockIdx.x, gridDim.x), smem);
 }
 
+// Persistent batched detector.  Work items are regions of all jobs
+// (item_job maps an item to its job).  Latencies are taken off the critical
+// path by working ahead:
+//   * the queue ticket of the item after next is drawn before the detection
+//     passes of the current region and resolved after them, so the atomic's
+//     round trip, and any wait for earlier stores, overlaps the passes;
+//   * when a region is a single fused sub-tile (and the workgroup has >= 256
+//     threads), the level-0 tile of the next region is loaded into registers
+//     during the passes of the current one.
 __global__ void __launch_bounds__(512) detect_batch_kernel(const fg_job *__restrict__ jobs,
-                                                           int njobs, int total,
-                                                           unsigned *counter) {
+                                                           const uint16_t *__restrict__ item_job,
+                                                           int total, unsigned *counter) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    __shared__ int s_item;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(&counter[0], 1u);
-        __syncthreads();
-        const int item = s_item;
-        if (item >= total) break;
-        int lo = 0, hi = njobs - 1;   // last job with region_base <= item
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (jobs[mid].region_base <= item) lo = mid;
-            else hi = mid - 1;
-        }
-        const fg_job &J = jobs[lo];   // uniform: read through the scalar cache
-        detect_region(J, item - J.region_base, smem);
+    // s_next[b] carries an item from thread 0 to the workgroup.  The item of
+    // iteration i+1 is written to s_next[b ^ 1] at the end of iteration i,
+    // and the two buffers alternate, so a value is never overwritten before
+    // every wave has read it.  Items are drawn from one atomic counter; a
+    // ticket at or past `total` means the queue is drained.
+    __shared__ int s_next[2];
+    uint32_t *keys = (uint32_t *)(smem + OFF_KEYS);
+    const bool pipe = blockDim.x >= 256;   // four tile rows per thread cover a fused tile
+    if (threadIdx.x == 0) {
+        const unsigned first = atomicAdd(&counter[0], 1u);
+        s_next[0] = first < (unsigned)total ? (int)first : total;
+        const unsigned second = first < (unsigned)total ? atomicAdd(&counter[0], 1u) : (unsigned)total;
+        s_next[1] = second < (unsigned)total ? (int)second : total;
     }
-    // The last workgroup out re-arms the queue for the next launch.
+    __syncthreads();
+    int item = s_next[0];
+    int b = 1;                             // s_next[b] holds the item after `item`
+    TileRegs T;
+    if (item < total && pipe) {
+        const fg_job &J = jobs[item_job[item]];
+        if (single_fused(J)) region_prefetch(J, item - J.region_base, T);
+    }
+    while (item < total) {
+        const fg_job &J = jobs[item_job[item]];   // uniform: read through the scalar cache
+        const int region = item - J.region_base;
+        const int next = s_next[b];
+        unsigned ticket = 0;
+        if (pipe && single_fused(J)) {
+            const Region R = region_of(J, region);
+            const Stage st = fused_stage(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1);
+            __syncthreads();   // the previous region is done with LDS
+            tile_commit(smem + T0, T, st.tw, st.th);
+            zero_lds(smem + OFF_M0, OFF_KEYS - OFF_M0);
+            keys_clear(keys, R.ncx * R.ncy);
+            Geo g0, g1, g2;
+            build_fused(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1, st, smem, g0, g1, g2);
+            if (next < total) {
+                const fg_job &Jn = jobs[item_job[next]];
+                if (single_fused(Jn)) region_prefetch(Jn, next - Jn.region_base, T);
+            }
+            if (threadIdx.x == 0 && next < total) ticket = atomicAdd(&counter[0], 1u);
+            run_passes(smem, g0, g1, g2, J.levels, R.P);
+            if (threadIdx.x == 0) s_next[b ^ 1] = next < total && ticket < (unsigned)total ? (int)ticket : total;
+            __syncthreads();   // publishes s_next[b ^ 1]
+            keys_write(J, R, keys);
+        } else {
+            if (threadIdx.x == 0 && next < total) ticket = atomicAdd(&counter[0], 1u);
+            detect_region(J, region, smem);
+            if (threadIdx.x == 0) s_next[b ^ 1] = next < total && ticket < (unsigned)total ? (int)ticket : total;
+            __syncthreads();
+            if (next < total && pipe) {
+                const fg_job &Jn = jobs[item_job[next]];
+                if (single_fused(Jn)) region_prefetch(Jn, next - Jn.region_base, T);
+            }
+        }
+        item = next;
+        b ^= 1;
+    }
+    // Every drawn ticket has been resolved.  The last workgroup out re-arms
+    // the queues for the next launch.
     if (threadIdx.x == 0) {
         __threadfence();
         const unsigned done = atomicAdd(&counter[1], 1u);
@@ -721,10 +866,13 @@ __device__ __forceinline__ void pyr_row_words(const uint8_t *src, int sp, uint8_
     const uint8_t *s1 = s0 + sp;
     uint8_t *d = dst + (size_t)y * dp + x;
     if (x + 4 <= dw) {
-        *(uint32_t *)d = halve4(*(const uint2 *)s0, *(const uint2 *)s1);
+        const u32x2 a = gload<u32x2>(s0), b = gload<u32x2>(s1);
+        gstore<uint32_t>(d, halve4(make_uint2(a.x, a.y), make_uint2(b.x, b.y)));
     } else {
         for (int q = 0; q < dw - x; ++q)
-            d[q] = (uint8_t)((s0[2 * q] + s0[2 * q + 1] + s1[2 * q] + s1[2 * q + 1] + 2) >> 2);
+            gstore<uint8_t>(d + q, (uint8_t)((gload<uint8_t>(s0 + 2 * q) + gload<uint8_t>(s0 + 2 * q + 1) +
+                                              gload<uint8_t>(s1 + 2 * q) + gload<uint8_t>(s1 + 2 * q + 1) + 2) >>
+                                             2));
     }
 }
 
@@ -783,9 +931,9 @@ hipError_t fg_launch_plain(const fg_job &j, const fg_launch &L, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t fg_launch_batch(const fg_job *jobs_dev, int njobs, int total, int max_levels,
-                           int max_w1, int max_h1, unsigned *counter, const fg_launch &L,
-                           hipStream_t s) {
+hipError_t fg_launch_batch(const fg_job *jobs_dev, const uint16_t *item_job, int njobs, int total,
+                           int max_levels, int max_w1, int max_h1, unsigned *counter,
+                           const fg_launch &L, hipStream_t s) {
     int mw = max_w1, mh = max_h1;
     for (int k = 1; k < max_levels && max_levels > MAX_FUSED; ++k) {
         dim3 grid(((mw + 3) / 4 + 63) / 64, mh, njobs);
@@ -799,6 +947,6 @@ hipError_t fg_launch_batch(const fg_job *jobs_dev, int njobs, int total, int max
     if (blocks > total) blocks = total;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(detect_batch_kernel, dim3(blocks), dim3(L.block), fg_smem_bytes(L.block), s,
-                       jobs_dev, njobs, total, counter);
+                       jobs_dev, item_job, total, counter);
     return hipGetLastError();
 }

@@ -25,17 +25,22 @@ constexpr int TABLE_SLOTS = 8;     // job tables that may be in flight at once
 struct TableSlot {
     fg_job *host = nullptr;        // pinned staging copy
     fg_job *dev = nullptr;
-    unsigned *counter = nullptr;   // persistent-queue counters (2 words)
+    unsigned *counter = nullptr;   // persistent-queue counters (FG_COUNTER_WORDS)
+    uint16_t *items_host = nullptr;   // pinned item -> job map
+    uint16_t *items_dev = nullptr;
+    int items_cap = 0;
     uint64_t ticket = 0;           // last submission that used this slot
 };
 
 struct Plan {
     bool live = false;
     fg_job *dev = nullptr;
+    uint16_t *items = nullptr;
     unsigned *counter = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int njobs = 0;
+    int total = 0, max_levels = 0, mw1 = 0, mh1 = 0;
 };
 
 }  // namespace
@@ -184,6 +189,14 @@ int build_table(fast_ctx *c, const fast_job *jobs, int njobs, fg_job *table, int
     return FAST_OK;
 }
 
+// items[i] = the job that owns work item i (regions in job order).
+void fill_items(const fg_job *table, int njobs, uint16_t *items) {
+    for (int j = 0; j < njobs; ++j) {
+        const int n = table[j].rx * table[j].ry;
+        for (int r = 0; r < n; ++r) items[table[j].region_base + r] = (uint16_t)j;
+    }
+}
+
 }  // namespace
 
 FG_API const char *fast_strerror(int status) {
@@ -235,12 +248,15 @@ FG_API void fast_ctx_destroy(fast_ctx *c) {
         if (p.exec) (void)hipGraphExecDestroy(p.exec);
         if (p.graph) (void)hipGraphDestroy(p.graph);
         if (p.dev) (void)hipFree(p.dev);
+        if (p.items) (void)hipFree(p.items);
         if (p.counter) (void)hipFree(p.counter);
     }
     for (auto &s : c->slots) {
         if (s.host) (void)hipHostFree(s.host);
         if (s.dev) (void)hipFree(s.dev);
         if (s.counter) (void)hipFree(s.counter);
+        if (s.items_host) (void)hipHostFree(s.items_host);
+        if (s.items_dev) (void)hipFree(s.items_dev);
     }
     for (auto &e : c->events)
         if (e) (void)hipEventDestroy(e);
@@ -337,18 +353,35 @@ FG_API int fast_submit(fast_ctx *c, const fast_job *jobs, int njobs, void *strea
         if (e != hipSuccess) { S.host = nullptr; return hip_fail(c, e, "hipHostMalloc job table"); }
         e = hipMalloc((void **)&S.dev, sizeof(fg_job) * FAST_MAX_JOBS);
         if (e != hipSuccess) { S.dev = nullptr; return hip_fail(c, e, "hipMalloc job table"); }
-        e = hipMalloc((void **)&S.counter, 2 * sizeof(unsigned));
+        e = hipMalloc((void **)&S.counter, FG_COUNTER_WORDS * sizeof(unsigned));
         if (e != hipSuccess) { S.counter = nullptr; return hip_fail(c, e, "hipMalloc counter"); }
-        e = hipMemset(S.counter, 0, 2 * sizeof(unsigned));
+        e = hipMemset(S.counter, 0, FG_COUNTER_WORDS * sizeof(unsigned));
         if (e != hipSuccess) return hip_fail(c, e, "hipMemset counter");
     }
     int total, max_levels, mw1, mh1;
     int rc = build_table(c, jobs, njobs, S.host, total, max_levels, mw1, mh1);
     if (rc) return rc;
+    if (total > S.items_cap) {
+        // the slot is idle, so its old map is no longer read by the device
+        if (S.items_host) (void)hipHostFree(S.items_host);
+        if (S.items_dev) (void)hipFree(S.items_dev);
+        S.items_host = nullptr;
+        S.items_dev = nullptr;
+        S.items_cap = 0;
+        const int cap = total > 65536 ? total : 65536;
+        hipError_t e = hipHostMalloc((void **)&S.items_host, sizeof(uint16_t) * cap, hipHostMallocDefault);
+        if (e != hipSuccess) { S.items_host = nullptr; return hip_fail(c, e, "hipHostMalloc item map"); }
+        e = hipMalloc((void **)&S.items_dev, sizeof(uint16_t) * cap);
+        if (e != hipSuccess) { S.items_dev = nullptr; return hip_fail(c, e, "hipMalloc item map"); }
+        S.items_cap = cap;
+    }
+    fill_items(S.host, njobs, S.items_host);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(S.dev, S.host, sizeof(fg_job) * njobs, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(c, e, "job table upload");
-    e = fg_launch_batch(S.dev, njobs, total, max_levels, mw1, mh1, S.counter, c->launch, s);
+    e = hipMemcpyAsync(S.items_dev, S.items_host, sizeof(uint16_t) * total, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(c, e, "item map upload");
+    e = fg_launch_batch(S.dev, S.items_dev, njobs, total, max_levels, mw1, mh1, S.counter, c->launch, s);
     if (e != hipSuccess) return hip_fail(c, e, "batch launch");
     rc = record_ticket(c, s, ticket);
     if (rc) return rc;
@@ -378,9 +411,10 @@ FG_API int fast_wait(fast_ctx *c, uint64_t ticket, int timeout_ms) {
     }
 }
 
-FG_API int fast_plan_create(fast_ctx *c, const fast_job *jobs, int njobs, int *plan_id) {
+FG_API int fast_plan_create(fast_ctx *c, const fast_job *jobs, int njobs, int flags, int *plan_id) {
     if (!c) return FAST_EINVAL;
     if (!plan_id) return fail(c, FAST_EINVAL, "plan_id is NULL");
+    if (flags & ~FAST_PLAN_GRAPH) return fail(c, FAST_EINVAL, "unknown plan flags");
     std::vector<fg_job> table((size_t)(njobs > 0 ? njobs : 1));
     int total, max_levels, mw1, mh1;
     int rc = build_table(c, jobs, njobs, table.data(), total, max_levels, mw1, mh1);
@@ -388,26 +422,42 @@ FG_API int fast_plan_create(fast_ctx *c, const fast_job *jobs, int njobs, int *p
     DeviceGuard g(c->device);
     Plan p;
     p.njobs = njobs;
+    p.total = total;
+    p.max_levels = max_levels;
+    p.mw1 = mw1;
+    p.mh1 = mh1;
+    std::vector<uint16_t> items((size_t)total);
+    fill_items(table.data(), njobs, items.data());
     hipError_t e = hipMalloc((void **)&p.dev, sizeof(fg_job) * njobs);
     if (e != hipSuccess) return hip_fail(c, e, "hipMalloc plan table");
-    e = hipMalloc((void **)&p.counter, 2 * sizeof(unsigned));
-    if (e != hipSuccess) { (void)hipFree(p.dev); return hip_fail(c, e, "hipMalloc plan counter"); }
-    e = hipMemcpy(p.dev, table.data(), sizeof(fg_job) * njobs, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(p.counter, 0, 2 * sizeof(unsigned));
-    if (e == hipSuccess && !c->capture_stream) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        hipError_t le = fg_launch_batch(p.dev, njobs, total, max_levels, mw1, mh1, p.counter, c->launch,
-                                        c->capture_stream);
-        e = hipStreamEndCapture(c->capture_stream, &p.graph);
-        if (le != hipSuccess) e = le;
+    e = hipMalloc((void **)&p.items, sizeof(uint16_t) * total);
+    if (e != hipSuccess) { (void)hipFree(p.dev); return hip_fail(c, e, "hipMalloc plan item map"); }
+    e = hipMalloc((void **)&p.counter, FG_COUNTER_WORDS * sizeof(unsigned));
+    if (e != hipSuccess) {
+        (void)hipFree(p.dev);
+        (void)hipFree(p.items);
+        return hip_fail(c, e, "hipMalloc plan counter");
     }
-    if (e == hipSuccess) e = hipGraphInstantiate(&p.exec, p.graph, nullptr, nullptr, 0);
+    e = hipMemcpy(p.dev, table.data(), sizeof(fg_job) * njobs, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p.items, items.data(), sizeof(uint16_t) * total, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p.counter, 0, FG_COUNTER_WORDS * sizeof(unsigned));
+    if (e == hipSuccess && (flags & FAST_PLAN_GRAPH)) {
+        if (!c->capture_stream) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = fg_launch_batch(p.dev, p.items, njobs, total, max_levels, mw1, mh1, p.counter,
+                                            c->launch, c->capture_stream);
+            e = hipStreamEndCapture(c->capture_stream, &p.graph);
+            if (le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&p.exec, p.graph, nullptr, nullptr, 0);
+    }
     if (e != hipSuccess) {
         if (p.graph) (void)hipGraphDestroy(p.graph);
         (void)hipFree(p.dev);
+        (void)hipFree(p.items);
         (void)hipFree(p.counter);
-        return hip_fail(c, e, "plan capture");
+        return hip_fail(c, e, "plan creation");
     }
     p.live = true;
     c->plans.push_back(p);
@@ -421,13 +471,13 @@ FG_API int fast_plan_launch(fast_ctx *c, int plan_id, void *stream, uint64_t *ti
         return fail(c, FAST_EINVAL, "unknown plan");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipGraphLaunch(c->plans[plan_id].exec, s);
-    if (e != hipSuccess) return hip_fail(c, e, "hipGraphLaunch");
-    uint64_t tk;
-    int rc = record_ticket(c, s, &tk);
-    if (rc) return rc;
-    if (ticket) *ticket = tk;
-    return FAST_OK;
+    const Plan &p = c->plans[plan_id];
+    hipError_t e = p.exec ? hipGraphLaunch(p.exec, s)
+                          : fg_launch_batch(p.dev, p.items, p.njobs, p.total, p.max_levels, p.mw1, p.mh1,
+                                            p.counter, c->launch, s);
+    if (e != hipSuccess) return hip_fail(c, e, p.exec ? "hipGraphLaunch" : "plan launch");
+    if (!ticket) return FAST_OK;
+    return record_ticket(c, s, ticket);
 }
 
 FG_API int fast_plan_destroy(fast_ctx *c, int plan_id) {
@@ -440,6 +490,7 @@ FG_API int fast_plan_destroy(fast_ctx *c, int plan_id) {
     if (p.exec) (void)hipGraphExecDestroy(p.exec);
     if (p.graph) (void)hipGraphDestroy(p.graph);
     (void)hipFree(p.dev);
+    (void)hipFree(p.items);
     (void)hipFree(p.counter);
     p = Plan();
     return FAST_OK;

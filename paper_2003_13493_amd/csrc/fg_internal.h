@@ -41,9 +41,14 @@ hipError_t fg_launch_plain(const fg_job &j, const fg_launch &L, hipStream_t s);
 // Pyramid only, one frame.
 hipError_t fg_launch_pyramid(const fg_job &j, hipStream_t s);
 
+// Words of the persistent batched kernel's counter buffer: the queue head and
+// the exit count (the rest is padding).
+constexpr int FG_COUNTER_WORDS = 16;
+
 // Batched path: `jobs_dev` is a device copy of njobs jobs whose region_base
-// fields are prefix sums; `total` is the number of work items; `counter` holds
-// two zero-initialised uint32 words that the kernel resets itself on exit.
-hipError_t fg_launch_batch(const fg_job *jobs_dev, int njobs, int total, int max_levels,
-                           int max_w1, int max_h1, unsigned *counter, const fg_launch &L,
-                           hipStream_t s);
+// fields are prefix sums; `total` is the number of work items and
+// `item_job[i]` the job of item i; `counter` holds FG_COUNTER_WORDS
+// zero-initialised words that the kernel re-arms itself on exit.
+hipError_t fg_launch_batch(const fg_job *jobs_dev, const uint16_t *item_job, int njobs, int total,
+                           int max_levels, int max_w1, int max_h1, unsigned *counter,
+                           const fg_launch &L, hipStream_t s);

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libfastgrid.so")
 
 FAST_OK, FAST_EINVAL, FAST_ENOMEM, FAST_EHIP, FAST_EBUSY, FAST_ETIMEDOUT = 0, -1, -2, -3, -4, -5
 FAST_MAX_LEVELS = 8
+FAST_PLAN_GRAPH = 1
 
 FEATURE_DTYPE = np.dtype([("x", "<u2"), ("y", "<u2"), ("score", "<u2"),
                           ("level", "u1"), ("reserved", "u1")])
@@ -72,7 +73,7 @@ def load() -> ctypes.CDLL:
             "fast_submit": ([vp, ctypes.POINTER(fast_job), i32, vp, u64p], i32),
             "fast_poll": ([vp, ctypes.c_uint64], i32),
             "fast_wait": ([vp, ctypes.c_uint64, i32], i32),
-            "fast_plan_create": ([vp, ctypes.POINTER(fast_job), i32, ctypes.POINTER(i32)], i32),
+            "fast_plan_create": ([vp, ctypes.POINTER(fast_job), i32, i32, ctypes.POINTER(i32)], i32),
             "fast_plan_launch": ([vp, i32, vp, u64p], i32),
             "fast_plan_destroy": ([vp, i32], i32),
             "fast_set_launch": ([vp, i32, i32, i32], i32),
@@ -152,13 +153,19 @@ def fast_wait(ctx, ticket: int, timeout_ms: int = -1) -> bool:
     return True
 
 
-def fast_plan_create(ctx, jobs, njobs: int) -> int:
+def fast_plan_create(ctx, jobs, njobs: int, flags: int = 0) -> int:
     pid = ctypes.c_int()
-    _check(ctx, load().fast_plan_create(ctx, jobs, njobs, ctypes.byref(pid)), "fast_plan_create")
+    _check(ctx, load().fast_plan_create(ctx, jobs, njobs, flags, ctypes.byref(pid)),
+           "fast_plan_create")
     return pid.value
 
 
-def fast_plan_launch(ctx, plan_id: int, stream=None) -> int:
+def fast_plan_launch(ctx, plan_id: int, stream=None, ticket: bool = True) -> int:
+    """Returns the ticket, or 0 when ticket=False (no completion event recorded)."""
+    if not ticket:
+        _check(ctx, load().fast_plan_launch(ctx, plan_id, _stream(stream), None),
+               "fast_plan_launch")
+        return 0
     tk = ctypes.c_uint64()
     _check(ctx, load().fast_plan_launch(ctx, plan_id, _stream(stream), ctypes.byref(tk)),
            "fast_plan_launch")
@@ -271,11 +278,11 @@ class Context:
     def wait(self, ticket: int, timeout_ms: int = -1) -> bool:
         return fast_wait(self.handle, ticket, timeout_ms)
 
-    def plan_create(self, jobs: ctypes.Array) -> int:
-        return fast_plan_create(self.handle, jobs, len(jobs))
+    def plan_create(self, jobs: ctypes.Array, graph: bool = False) -> int:
+        return fast_plan_create(self.handle, jobs, len(jobs), FAST_PLAN_GRAPH if graph else 0)
 
-    def plan_launch(self, plan_id: int, stream=None) -> int:
-        return fast_plan_launch(self.handle, plan_id, stream)
+    def plan_launch(self, plan_id: int, stream=None, ticket: bool = True) -> int:
+        return fast_plan_launch(self.handle, plan_id, stream, ticket)
 
     def plan_destroy(self, plan_id: int) -> None:
         fast_plan_destroy(self.handle, plan_id)

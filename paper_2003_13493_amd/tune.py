@@ -4,8 +4,8 @@ Candidates are (region, block, persistent blocks per CU): the side of the
 level-0 region a workgroup owns, the workgroup size (waves per region) and the
 occupancy target of the persistent kernel.  Every candidate is first run once
 and its output compared bit for bit with the output of the reference shape on
-the same frames; only candidates that match are timed.  Timing is the median
-of graph replays measured with device events.
+the same frames; only candidates that match are timed.  Timing is the mean
+of back-to-back launches of a resident plan, measured with device events.
 
 Results are cached as JSON keyed by the workload signature (frame sizes,
 levels, cells), so a serving process can load the tuned shape at start-up.
@@ -53,21 +53,21 @@ class _Resident:
 
 
 def _time_plan(ctx, res, reps: int, warmup: int) -> float:
+    """Mean ms per launch over reps back-to-back launches (device events)."""
     import torch
     pid = ctx.plan_create(res.jobs)
     try:
         stream = torch.cuda.current_stream()
         for _ in range(warmup):
-            ctx.plan_launch(pid, stream)
+            ctx.plan_launch(pid, stream, ticket=False)
         torch.cuda.synchronize()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
-        ev[0].record(stream)
-        for i in range(reps):
-            ctx.plan_launch(pid, stream)
-            ev[i + 1].record(stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            ctx.plan_launch(pid, stream, ticket=False)
+        e1.record(stream)
         torch.cuda.synchronize()
-        ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
-        return float(np.median(ms))
+        return e0.elapsed_time(e1) / reps
     finally:
         ctx.plan_destroy(pid)
 

@@ -85,11 +85,12 @@ def test_submit_back_to_back_reuses_queue(ctx, batch):
     assert all(ctx.poll(t) for t in tickets)
 
 
-def test_plan_graph_replays(ctx, batch):
+@pytest.mark.parametrize("graph", [False, True], ids=["direct", "graph"])
+def test_plan_replays(ctx, batch, graph):
     specs, frames, want = batch
-    print("case plan replays", flush=True)
+    print(f"case plan replays graph={graph}", flush=True)
     pyrs, grids, jobs = make_resident(specs, frames)
-    pid = ctx.plan_create(jobs)
+    pid = ctx.plan_create(jobs, graph=graph)
     try:
         for r in range(4):
             for g in grids:
@@ -98,11 +99,56 @@ def test_plan_graph_replays(ctx, batch):
                 for t in p.tensors[1:]:
                     t.fill_(0)
             torch.cuda.synchronize()
-            tk = ctx.plan_launch(pid)
-            assert ctx.wait(tk, 60_000)
+            if r % 2:
+                assert ctx.plan_launch(pid, ticket=False) == 0
+                torch.cuda.synchronize()
+            else:
+                tk = ctx.plan_launch(pid)
+                assert ctx.wait(tk, 60_000)
             check_all(specs, pyrs, grids, want, f"replay {r}")
     finally:
         ctx.plan_destroy(pid)
+
+
+@pytest.mark.parametrize("graph", [False, True], ids=["direct", "graph"])
+def test_plan_mixed_levels(ctx, graph):
+    """Frames with 1..5 levels in one plan: levels 4.. need the separate pyramid
+    kernels before the persistent launch."""
+    rng = np.random.default_rng(31)
+    specs, frames, want = [], [], []
+    for i in range(10):
+        levels = 1 + i % 5
+        w = int(rng.integers(7 << (levels - 1), 500))
+        h = int(rng.integers(7 << (levels - 1), 400))
+        cell = max(16, 1 << (levels - 1))
+        s = synth.FrameSpec(w, h, levels, synth.BATCH_T[i % 4], synth.BATCH_N[i % 3], cell,
+                            seed=600 + i, nshapes=60, sigma=4.0)
+        img = s.make()
+        specs.append(s)
+        frames.append(img)
+        slots, planes = oracle.detect_grid(img, w, levels, s.t, s.n, cell)
+        want.append((slots, [p[:, :pw].copy() for p, pw in planes]))
+    print(f"case plan mixed levels graph={graph}", flush=True)
+    pyrs, grids, jobs = make_resident(specs, frames)
+    pid = ctx.plan_create(jobs, graph=graph)
+    try:
+        for r in range(2):
+            for g in grids:
+                g.tensor.fill_(0x77)
+            torch.cuda.synchronize()
+            ctx.plan_launch(pid, ticket=False)
+            torch.cuda.synchronize()
+            check_all(specs, pyrs, grids, want, f"mixed replay {r}")
+    finally:
+        ctx.plan_destroy(pid)
+
+
+def test_plan_rejects_unknown_flags(ctx, batch):
+    specs, frames, _ = batch
+    pyrs, grids, jobs = make_resident(specs[:2], frames[:2])
+    with pytest.raises(fastgrid.FastError) as ei:
+        fastgrid.fast_plan_create(ctx.handle, jobs, 2, 6)
+    assert ei.value.code == fastgrid.FAST_EINVAL
 
 
 def test_batch_equals_plain_per_frame(ctx, batch):
