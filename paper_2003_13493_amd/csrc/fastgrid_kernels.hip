@@ -57,10 +57,9 @@ constexpr int M1_ROWS = SUB / 2 + 2, M1_P = SUB / 2 + 4;
 constexpr int M2_ROWS = SUB / 4 + 2, M2_P = SUB / 4 + 4;
 constexpr int MAX_RCELLS = 16;
 constexpr int MAX_KEYS = MAX_RCELLS * MAX_RCELLS;
-// Per-wave scratch: the candidate list of one part (<= 18 scored rows of each
-// level: 18*72 + 10*40 + 6*24 = 1840 pixels).
-constexpr int LIST_CAP = 1856;
-constexpr int BLIST_CAP = 164;             // groups of 8 of one segment: <= 18 * 9
+// Groups of 8 pixels scored per sub-tile, at most: every level's area plus a
+// 1-pixel ring, in whole groups (66 x 9 + 34 x 5 + 18 x 3 for three levels).
+constexpr int MAX_GROUPS = 66 * 9 + 34 * 5 + 18 * 3;
 constexpr uint16_t NO_ENTRY = 0xFFFF;
 
 constexpr int OFF_M0 = TILE_BYTES;
@@ -68,12 +67,23 @@ constexpr int OFF_M1 = OFF_M0 + M0_ROWS * M0_P * 2;
 constexpr int OFF_M2 = OFF_M1 + M1_ROWS * M1_P * 2;
 constexpr int OFF_KEYS = (OFF_M2 + M2_ROWS * M2_P * 2 + 15) & ~15;
 constexpr int OFF_WAVES = OFF_KEYS + MAX_KEYS * 4;
-constexpr int WAVE_BYTES = BLIST_CAP * 4 + (LIST_CAP + 64) * 2;   // + one spare slot per lane
-static_assert(OFF_WAVES % 16 == 0 && WAVE_BYTES % 16 == 0, "aligned scratch");
+static_assert(OFF_WAVES % 16 == 0, "aligned scratch");
+
+// Per-wave scratch for V waves.  Compass rounds are dealt to the waves in
+// turn, so a wave sees at most ceil(MAX_GROUPS / 64V) rounds of 64 groups:
+// its group list holds that many words and its pixel list eight pixels per
+// group, plus one spare slot per lane.
+__host__ __device__ constexpr int blist_cap(int waves) {
+    return (MAX_GROUPS + 64 * waves - 1) / (64 * waves) * 64;
+}
+__host__ __device__ constexpr int list_cap(int waves) { return 8 * blist_cap(waves); }
+__host__ __device__ constexpr int wave_bytes(int waves) {
+    return (blist_cap(waves) * 4 + (list_cap(waves) + 64) * 2 + 15) & ~15;
+}
 
 }  // namespace
 
-size_t fg_smem_bytes(int block) { return (size_t)OFF_WAVES + (size_t)(block / 64) * WAVE_BYTES; }
+size_t fg_smem_bytes(int block) { return (size_t)OFF_WAVES + (size_t)(block / 64) * wave_bytes(block / 64); }
 
 namespace {
 
@@ -221,30 +231,61 @@ __device__ __forceinline__ void set_groups(Geo &g) {
 
 __device__ __forceinline__ bool has_area(const Geo &g) { return g.ex > g.sx && g.ey > g.sy; }
 
-// P1+P2 for one segment: compass test of every scored pixel (8 per lane and
-// round, packed 16-bit lanes).  Groups of 8 with a survivor are compacted
-// first (ballot + mbcnt into the byte list, one 32-bit word per group:
-// LDS offset of its first pixel << 8 | survivor mask); the survivors of the
-// byte list are then expanded into the pixel list with one wave prefix sum.
-// Pixel entries are (level << 14) | (LDS offset of the pixel); pixels
-// outside the testable area (3 <= x <= W-4, 3 <= y <= H-4, inside the scored
-// ring) become NO_ENTRY.  Returns the new pixel count (wave-uniform).
+__device__ __forceinline__ int sel3(int l, int a, int b, int c) { return l == 0 ? a : (l == 1 ? b : c); }
+
+// Scored area of one level in a sub-tile: rows [r0, r0 + nrows) of the tile
+// band, groups of 8 pixels from column gc0, ppr groups per row; pixels
+// outside [c_lo, c_hi] x [r_lo, r_hi] (tile coordinates) are not testable.
+struct Seg {
+    int tbase, r0, nrows, gc0, ppr, n;   // n = nrows * ppr groups
+    int c_lo, c_hi, r_lo, r_hi;
+};
+
+__device__ __forceinline__ Seg make_seg(const Geo &g, bool on) {
+    Seg q;
+    q.tbase = g.tbase;
+    q.r0 = g.sy - 1 - g.ty;
+    q.nrows = on ? g.ey - g.sy + 2 : 0;
+    q.gc0 = g.gc0;
+    q.ppr = g.ncolg >> 1;
+    q.n = q.nrows * q.ppr;
+    q.c_lo = max(g.sx - 1, 3) - g.tx;
+    q.c_hi = min(g.ex, g.W - 4) - g.tx;
+    q.r_lo = max(q.r0, 3 - g.ty);
+    q.r_hi = min(q.r0 + q.nrows - 1, g.H - 4 - g.ty);
+    return q;
+}
+
+// P1+P2: compass test of every scored pixel of every level, 8 pixels per
+// lane in packed 16-bit lanes.  The groups of all levels form one sequence
+// dealt to the waves round-robin in rounds of 64, so every wave does the
+// same share whatever the level sizes.  Groups with a survivor are compacted
+// into the wave's group list (ballot + mbcnt; word = level << 22 | LDS
+// offset of the group << 8 | survivor mask), which is then expanded into the
+// wave's pixel list, keeping testable pixels only; an entry is
+// (level << 14) | LDS offset of the pixel.  Returns the wave's pixel count.
 template <int K>
-__device__ int seg_collect(const uint8_t *smem, int tbase, int r_first, int nrows, int gc0, int ncolg,
-                           int t, uint32_t tag, int c_lo, int c_hi, int r_lo, int r_hi,
-                           uint32_t *blist, uint16_t *list, int count) {
-    const int lane = lane_id();
-    const int ppr = ncolg >> 1;                 // groups of 8 pixels per row
-    const int total = nrows * ppr;              // <= 18 * 9
-    const float inv_ppr = 1.0f / (float)ppr;    // (i + 0.5) * inv_ppr is exact for i < 256
+__device__ int collect(const uint8_t *smem, const Seg &s0, const Seg &s1, const Seg &s2, int t,
+                       uint32_t *blist, uint16_t *list) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int total = s0.n + s1.n + s2.n;
+    const int b1 = s0.n, b2 = s0.n + s1.n;
+    const float inv0 = 1.0f / (float)max(s0.ppr, 1), inv1 = 1.0f / (float)max(s1.ppr, 1),
+                inv2 = 1.0f / (float)max(s2.ppr, 1);
     const s16x2 T1 = {(short)(t + 1), (short)(t + 1)};
     int nb = 0;
-    for (int i0 = 0; i0 < total; i0 += 64) {
+    for (int i0 = wave * 64; i0 < total; i0 += nwaves * 64) {
         const int i = i0 + lane;
-        uint32_t sv = 0, off = 0;
+        uint32_t sv = 0, off = 0, lvl = 0;
         if (i < total) {
-            const int row = (int)(((float)i + 0.5f) * inv_ppr), pp = i - row * ppr;
-            off = (uint32_t)(tbase + (r_first + row) * LP + gc0 + 8 * pp);
+            lvl = i < b1 ? 0u : (i < b2 ? 1u : 2u);
+            const int local = i - (lvl == 0 ? 0 : (lvl == 1 ? b1 : b2));
+            const int ppr = sel3(lvl, s0.ppr, s1.ppr, s2.ppr);
+            const float inv = lvl == 0 ? inv0 : (lvl == 1 ? inv1 : inv2);
+            const int row = (int)(((float)local + 0.5f) * inv), pp = local - row * ppr;
+            off = (uint32_t)(sel3(lvl, s0.tbase, s1.tbase, s2.tbase) +
+                             (sel3(lvl, s0.r0, s1.r0, s2.r0) + row) * LP + sel3(lvl, s0.gc0, s1.gc0, s2.gc0) +
+                             8 * pp);
             if constexpr (K > 0) {
                 const uint8_t *p = smem + off;
                 const uint32_t D0 = *(const uint32_t *)(p - 4);
@@ -279,40 +320,44 @@ __device__ int seg_collect(const uint8_t *smem, int tbase, int r_first, int nrow
         const uint64_t bal = __ballot(sv != 0);
         const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        if (sv) blist[nb + rank] = (off << 8) | sv;
+        if (sv) blist[nb + rank] = (lvl << 22) | (off << 8) | sv;
         nb += __popcll(bal);
     }
     wave_sync();
+    int count = 0;
+    const int spare = list_cap(nwaves) + lane;
     for (int j0 = 0; j0 < nb; j0 += 64) {
         const int j = j0 + lane;
         const uint32_t w = j < nb ? blist[j] : 0u;
-        const uint32_t m = w & 0xFFu;
+        const uint32_t l = w >> 22;
+        const int off0 = (int)((w >> 8) & 0x3FFFu);
+        const int rel = off0 - sel3(l, s0.tbase, s1.tbase, s2.tbase);
+        const int r = (int)(((uint32_t)rel * 18725u) >> 21);   // rel / LP
+        const int c0 = rel - r * LP;
+        const int c_lo = sel3(l, s0.c_lo, s1.c_lo, s2.c_lo), c_hi = sel3(l, s0.c_hi, s1.c_hi, s2.c_hi);
+        const bool row_ok = r >= sel3(l, s0.r_lo, s1.r_lo, s2.r_lo) && r <= sel3(l, s0.r_hi, s1.r_hi, s2.r_hi);
+        // bit b of the mask is pixel q(b) = 2 (b & 3) + (b >> 2) of the group
+        uint32_t m = 0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int c = c0 + (((b & 3) << 1) | (b >> 2));
+            m |= (row_ok && c >= c_lo && c <= c_hi ? 1u : 0u) << b;
+        }
+        m &= w;
         const int cnt = __builtin_popcount(m);
         const int incl = wave_scan(cnt);
         const int pos = count + incl - cnt;
         count += __builtin_amdgcn_readlane(incl, 63);
-        const int off0 = (int)(w >> 8);
-        const int rel = off0 - tbase;
-        const int r = (int)(((uint32_t)rel * 18725u) >> 21);   // rel / LP
-        const int c0 = rel - r * LP;
-        const bool row_ok = r >= r_lo && r <= r_hi;
-        const uint32_t base = (tag << 14) | (uint32_t)off0;
-        // Bit b of the mask is pixel q(b) of the group (see the packing
-        // above); a set bit is written at pos + (set bits below it).  Clear
-        // bits write to the lane's own slot past the list, so the loop has
-        // no branches.
-        const int spare = LIST_CAP + lane;
+        const uint32_t base = (l << 14) | (uint32_t)off0;
+        // a kept pixel goes to pos + (kept pixels before it); the others write
+        // to the lane's spare slot, so the loop has no branches
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
-            const int q = ((b & 3) << 1) | (b >> 2);
-            int at = pos + __builtin_popcount(m & ((1u << b) - 1u));
-            at = ((m >> b) & 1u) && at < LIST_CAP ? at : spare;
-            const int c = c0 + q;
-            const bool ok = row_ok && c >= c_lo && c <= c_hi;
-            list[at] = ok ? (uint16_t)(base + (uint32_t)q) : NO_ENTRY;
+            const int at = (m >> b) & 1u ? pos + __builtin_popcount(m & ((1u << b) - 1u)) : spare;
+            list[at] = (uint16_t)(base + (uint32_t)(((b & 3) << 1) | (b >> 2)));
         }
     }
-    return count < LIST_CAP ? count : LIST_CAP;
+    return count;
 }
 
 // P3: keep entries that pass the 8-point test, compacted in place.
@@ -348,7 +393,6 @@ __device__ int pass_even8(const uint8_t *smem, int t, int k8, uint16_t *list, in
     return n2;
 }
 
-__device__ __forceinline__ int sel3(int l, int a, int b, int c) { return l == 0 ? a : (l == 1 ? b : c); }
 
 // Row and column inside the LDS tile band of an entry's offset.
 __device__ __forceinline__ void tile_rc(uint32_t off, int &row, int &col) {
@@ -381,41 +425,36 @@ __device__ __forceinline__ LevelMap level_map(const Geo &g, int band_row, int ba
     return m;
 }
 
-// One pass of a wave: segments [ra_l, rb_l) of up to three levels (empty
-// when ra_l == rb_l), each scored with a 1-row ring.  P1..P5 run once over
-// the whole pass.
-__device__ void process_pass(uint8_t *smem, const Geo &g0, const Geo &g1, const Geo &g2,
-                             const int ra[3], const int rb[3], const Params &P, uint32_t *blist,
-                             uint16_t *list, uint32_t *keys) {
-    const Geo *gs[3] = {&g0, &g1, &g2};
+// Detect levels g0..g(nl-1) of the staged sub-tile (score maps zeroed) and
+// fold the survivors into the region's cell keys.  P1-P4 run on every wave
+// without workgroup barriers; one barrier makes all scores visible before
+// NMS.
+__device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Geo &g2, int nl,
+                           const Params &P) {
+    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    uint8_t *scratch = smem + OFF_WAVES + wave * wave_bytes(nwaves);
+    uint32_t *blist = (uint32_t *)scratch;
+    uint16_t *list = (uint16_t *)(scratch + blist_cap(nwaves) * 4);
+    uint32_t *keys = (uint32_t *)(smem + OFF_KEYS);
+    const Seg s0 = make_seg(g0, has_area(g0));
+    const Seg s1 = make_seg(g1, nl > 1 && has_area(g1));
+    const Seg s2 = make_seg(g2, nl > 2 && has_area(g2));
     int n1 = 0;
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        if (ra[l] >= rb[l]) continue;
-        const Geo &g = *gs[l];
-        const int r_first = ra[l] - 1 - g.ty;
-        const int nrows = rb[l] - ra[l] + 2;
-        const int c_lo = max(g.sx - 1, 3) - g.tx, c_hi = min(g.ex, g.W - 4) - g.tx;
-        const int r_lo = max(r_first, 3 - g.ty);
-        const int r_hi = min(r_first + nrows - 1, g.H - 4 - g.ty);
-#define FG_COLLECT(KK) n1 = seg_collect<KK>(smem, g.tbase, r_first, nrows, g.gc0, g.ncolg, P.t, \
-                                            (uint32_t)l, c_lo, c_hi, r_lo, r_hi, blist, list, n1)
-        switch (P.kc) {
-            case 0: FG_COLLECT(0); break;
-            case 1: FG_COLLECT(1); break;
-            case 2: FG_COLLECT(2); break;
-            case 3: FG_COLLECT(3); break;
-            default: FG_COLLECT(4); break;
-        }
-#undef FG_COLLECT
+    switch (P.kc) {
+        case 0: n1 = collect<0>(smem, s0, s1, s2, P.t, blist, list); break;
+        case 1: n1 = collect<1>(smem, s0, s1, s2, P.t, blist, list); break;
+        case 2: n1 = collect<2>(smem, s0, s1, s2, P.t, blist, list); break;
+        case 3: n1 = collect<3>(smem, s0, s1, s2, P.t, blist, list); break;
+        default: n1 = collect<4>(smem, s0, s1, s2, P.t, blist, list); break;
     }
     wave_sync();
     const int n2 = pass_even8(smem, P.t, P.k8, list, n1);
-    const LevelMap m0 = level_map(g0, 0, T0, ra[0], rb[0], P);
-    const LevelMap m1 = level_map(g1, 96, T1 - 96 * LP, ra[1], rb[1], P);
-    const LevelMap m2 = level_map(g2, 96, T2 - 96 * LP, ra[2], rb[2], P);
+    const LevelMap m0 = level_map(g0, 0, T0, g0.sy, g0.ey, P);
+    const LevelMap m1 = level_map(g1, 96, T1 - 96 * LP, g1.sy, g1.ey, P);
+    const LevelMap m2 = level_map(g2, 96, T2 - 96 * LP, g2.sy, g2.ey, P);
     uint16_t *maps = (uint16_t *)smem;
     const int lane = lane_id();
+    // P4: full segment test and score into the level's score map
     for (int i = lane; i < n2; i += 64) {
         const uint16_t e = list[i];
         const uint32_t s = full_score(smem + (e & 0x3FFF), P.t, P.n);
@@ -427,7 +466,8 @@ __device__ void process_pass(uint8_t *smem, const Geo &g0, const Geo &g1, const 
                 (uint16_t)s;
         }
     }
-    wave_sync();
+    __syncthreads();   // every level's scores, ring included, are in the maps
+    // P5: 3x3 NMS of the sub-tile's own pixels, then the cell keys
     for (int i = lane; i < n2; i += 64) {
         const uint16_t e = list[i];
         const int l = e >> 14;
@@ -435,7 +475,7 @@ __device__ void process_pass(uint8_t *smem, const Geo &g0, const Geo &g1, const 
         tile_rc(e & 0x3FFF, row, col);
         if (row < sel3(l, m0.rlo, m1.rlo, m2.rlo) || row >= sel3(l, m0.rhi, m1.rhi, m2.rhi) ||
             col < sel3(l, m0.clo, m1.clo, m2.clo) || col >= sel3(l, m0.chi, m1.chi, m2.chi))
-            continue;   // ring pixel: another pass owns its suppression
+            continue;   // ring pixel: its own sub-tile suppresses it
         const int mp = sel3(l, m0.mp, m1.mp, m2.mp);
         const uint16_t *q = maps + row * mp + col + sel3(l, m0.mbias, m1.mbias, m2.mbias);
         const uint32_t s = q[0];
@@ -450,36 +490,8 @@ __device__ void process_pass(uint8_t *smem, const Geo &g0, const Geo &g1, const 
         const int oy = row + sel3(l, m0.yo, m1.yo, m2.yo);
         const int cy = oy / cw, cx = ox / cw;
         const uint32_t local = (uint32_t)((oy - cy * cw) * cw + (ox - cx * cw));
-        const uint32_t key = (s << 19) | ((uint32_t)(7 - (gs[0]->k + l)) << 16) | (0xFFFFu - local);
+        const uint32_t key = (s << 19) | ((uint32_t)(7 - (g0.k + l)) << 16) | (0xFFFFu - local);
         atomicMax(&keys[cy * P.ncx + cx], key);
-    }
-    wave_sync();
-}
-
-// Rows [sy, ey) of a level are cut into V equal slices (V = max(4, waves),
-// a power of two); part p takes slice p of every level, so a part never holds
-// more than 16 + 2 scored rows of any level.
-__device__ __forceinline__ void part_rows(const Geo &g, int vshift, int p, int &ra, int &rb) {
-    const int h = g.ey - g.sy;
-    const int q = (h + (1 << vshift) - 1) >> vshift;
-    ra = min(g.sy + p * q, g.ey);
-    rb = min(ra + q, g.ey);
-}
-
-// Detect levels g0..g(nl-1) of the staged sub-tile on all waves.
-__device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Geo &g2, int nl,
-                           const Params &P) {
-    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    uint32_t *blist = (uint32_t *)(smem + OFF_WAVES + wave * WAVE_BYTES);
-    uint16_t *list = (uint16_t *)(smem + OFF_WAVES + wave * WAVE_BYTES + BLIST_CAP * 4);
-    uint32_t *keys = (uint32_t *)(smem + OFF_KEYS);
-    const int vshift = nwaves >= 8 ? 3 : 2;
-    for (int p = wave; p < (1 << vshift); p += nwaves) {
-        int ra[3] = {0, 0, 0}, rb[3] = {0, 0, 0};
-        if (has_area(g0)) part_rows(g0, vshift, p, ra[0], rb[0]);
-        if (nl > 1 && has_area(g1)) part_rows(g1, vshift, p, ra[1], rb[1]);
-        if (nl > 2 && has_area(g2)) part_rows(g2, vshift, p, ra[2], rb[2]);
-        process_pass(smem, g0, g1, g2, ra, rb, P, blist, list, keys);
     }
 }
 
