@@ -790,9 +790,11 @@ __global__ void __launch_bounds__(512) detect_plain_kernel(fg_job J) {
 // Persistent batched detector.  Work items are regions of all jobs
 // (item_job maps an item to its job).  Latencies are taken off the critical
 // path by working ahead:
-//   * the queue ticket of the item after next is drawn before the detection
-//     passes of the current region and resolved after them, so the atomic's
-//     round trip, and any wait for earlier stores, overlaps the passes;
+//   * the first two items of a workgroup are fixed, and the queue ticket of
+//     the item after next is drawn before the detection passes of the
+//     current region and resolved after them, so the atomic's round trip,
+//     and any wait for earlier stores, overlaps the passes;
+//   * the job of the next item is looked up while the current one is staged;
 //   * when a region is a single fused sub-tile (and the workgroup has >= 256
 //     threads), the level-0 tile of the next region is loaded into registers
 //     during the passes of the current one.
@@ -800,32 +802,30 @@ __global__ void __launch_bounds__(512) detect_batch_kernel(const fg_job *__restr
                                                            const uint16_t *__restrict__ item_job,
                                                            int total, unsigned *counter) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    // s_next[b] carries an item from thread 0 to the workgroup.  The item of
-    // iteration i+1 is written to s_next[b ^ 1] at the end of iteration i,
-    // and the two buffers alternate, so a value is never overwritten before
-    // every wave has read it.  Items are drawn from one atomic counter; a
-    // ticket at or past `total` means the queue is drained.
+    // Work items: workgroup g starts with items g and g + G (G blocks, at most
+    // `total`); the rest are handed out by an atomic counter, ticket k being
+    // item 2G + k.  A workgroup always knows its current and its next item,
+    // and draws the ticket of the one after during the current detection.
+    // s_next[b] carries that item from thread 0 to the workgroup; the two
+    // buffers alternate, so a value is never overwritten before every wave
+    // has read it.
     __shared__ int s_next[2];
     uint32_t *keys = (uint32_t *)(smem + OFF_KEYS);
     const bool pipe = blockDim.x >= 256;   // four tile rows per thread cover a fused tile
-    if (threadIdx.x == 0) {
-        const unsigned first = atomicAdd(&counter[0], 1u);
-        s_next[0] = first < (unsigned)total ? (int)first : total;
-        const unsigned second = first < (unsigned)total ? atomicAdd(&counter[0], 1u) : (unsigned)total;
-        s_next[1] = second < (unsigned)total ? (int)second : total;
-    }
-    __syncthreads();
-    int item = s_next[0];
-    int b = 1;                             // s_next[b] holds the item after `item`
+    const int G = (int)gridDim.x;
+    int item = (int)blockIdx.x;
+    int next = item + G < total ? item + G : total;
+    int jl = item_job[item];
+    int b = 0;
     TileRegs T;
-    if (item < total && pipe) {
-        const fg_job &J = jobs[item_job[item]];
+    if (pipe) {
+        const fg_job &J = jobs[jl];
         if (single_fused(J)) region_prefetch(J, item - J.region_base, T);
     }
     while (item < total) {
-        const fg_job &J = jobs[item_job[item]];   // uniform: read through the scalar cache
+        const fg_job &J = jobs[jl];   // uniform: read through the scalar cache
         const int region = item - J.region_base;
-        const int next = s_next[b];
+        const int jn = next < total ? (int)item_job[next] : 0;   // issued early, used after staging
         unsigned ticket = 0;
         if (pipe && single_fused(J)) {
             const Region R = region_of(J, region);
@@ -837,25 +837,34 @@ __global__ void __launch_bounds__(512) detect_batch_kernel(const fg_job *__restr
             Geo g0, g1, g2;
             build_fused(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1, st, smem, g0, g1, g2);
             if (next < total) {
-                const fg_job &Jn = jobs[item_job[next]];
+                const fg_job &Jn = jobs[jn];
                 if (single_fused(Jn)) region_prefetch(Jn, next - Jn.region_base, T);
             }
             if (threadIdx.x == 0 && next < total) ticket = atomicAdd(&counter[0], 1u);
             run_passes(smem, g0, g1, g2, J.levels, R.P);
-            if (threadIdx.x == 0) s_next[b ^ 1] = next < total && ticket < (unsigned)total ? (int)ticket : total;
-            __syncthreads();   // publishes s_next[b ^ 1]
+            if (threadIdx.x == 0) {
+                const unsigned cand = 2u * (unsigned)G + ticket;
+                s_next[b] = next < total && cand < (unsigned)total ? (int)cand : total;
+            }
+            __syncthreads();   // publishes s_next[b]
             keys_write(J, R, keys);
         } else {
             if (threadIdx.x == 0 && next < total) ticket = atomicAdd(&counter[0], 1u);
             detect_region(J, region, smem);
-            if (threadIdx.x == 0) s_next[b ^ 1] = next < total && ticket < (unsigned)total ? (int)ticket : total;
+            if (threadIdx.x == 0) {
+                const unsigned cand = 2u * (unsigned)G + ticket;
+                s_next[b] = next < total && cand < (unsigned)total ? (int)cand : total;
+            }
             __syncthreads();
             if (next < total && pipe) {
-                const fg_job &Jn = jobs[item_job[next]];
+                const fg_job &Jn = jobs[jn];
                 if (single_fused(Jn)) region_prefetch(Jn, next - Jn.region_base, T);
             }
         }
+        const int after = s_next[b];
         item = next;
+        next = after;
+        jl = jn;
         b ^= 1;
     }
     // Every drawn ticket has been resolved.  The last workgroup out re-arms
