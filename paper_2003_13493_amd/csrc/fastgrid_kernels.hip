@@ -555,14 +555,33 @@ __device__ __forceinline__ uint32_t halve4(uint2 a, uint2 b) {
     return __builtin_amdgcn_perm((s1 >> 2) & m, (s0 >> 2) & m, 0x06040200u);
 }
 
-// Build an LDS level from the level above it (tile origins halve exactly;
-// tw is the destination width, a multiple of 4, at most 64).
-__device__ void halve_tile(const uint8_t *src, uint8_t *dst, int tw, int th) {
-    const int d = threadIdx.x & 15;              // 16 word slots per row
-    if (4 * d >= tw) return;
-    for (int r = threadIdx.x >> 4; r < th; r += blockDim.x >> 4) {
-        const uint8_t *s = src + (2 * r) * LP + 8 * d;
-        *(uint32_t *)(dst + r * LP + 4 * d) = halve4(*(const uint2 *)s, *(const uint2 *)(s + LP));
+// Levels 1 and 2 of a fused tile in one pass (tw a multiple of 16): a task
+// reads a 16 x 4 block of level 0 and writes the 8 x 2 level-1 block and the
+// 4 x 1 level-2 block it covers, each by successive (a+b+c+d+2)>>2 rounding.
+// With an odd number of level-1 rows the last one has tasks of its own.
+__device__ void halve_two(const uint8_t *l0, uint8_t *l1, uint8_t *l2, int tw, int th, bool need_l2) {
+    const int wpr = tw >> 4, rows2 = th >> 2;
+    const int tasks = wpr * rows2 + (((th >> 1) & 1) ? wpr : 0);
+    for (int i = threadIdx.x; i < tasks; i += blockDim.x) {
+        const int y2 = i / wpr, x4 = i - y2 * wpr;
+        const uint8_t *s = l0 + (4 * y2) * LP + 16 * x4;
+        if (y2 < rows2) {
+            const u32x4 a = *(const u32x4 *)s, b = *(const u32x4 *)(s + LP);
+            const u32x4 c = *(const u32x4 *)(s + 2 * LP), d = *(const u32x4 *)(s + 3 * LP);
+            const uint32_t r0a = halve4(make_uint2(a.x, a.y), make_uint2(b.x, b.y));
+            const uint32_t r0b = halve4(make_uint2(a.z, a.w), make_uint2(b.z, b.w));
+            const uint32_t r1a = halve4(make_uint2(c.x, c.y), make_uint2(d.x, d.y));
+            const uint32_t r1b = halve4(make_uint2(c.z, c.w), make_uint2(d.z, d.w));
+            *(uint2 *)(l1 + (2 * y2) * LP + 8 * x4) = make_uint2(r0a, r0b);
+            *(uint2 *)(l1 + (2 * y2 + 1) * LP + 8 * x4) = make_uint2(r1a, r1b);
+            if (need_l2) *(uint32_t *)(l2 + y2 * LP + 4 * x4) = halve4(make_uint2(r0a, r0b), make_uint2(r1a, r1b));
+        } else {
+            // last level-1 row, 2 * rows2, from level-0 rows 4 * rows2 and 4 * rows2 + 1
+            const u32x4 a = *(const u32x4 *)s, b = *(const u32x4 *)(s + LP);
+            *(uint2 *)(l1 + (2 * y2) * LP + 8 * x4) =
+                make_uint2(halve4(make_uint2(a.x, a.y), make_uint2(b.x, b.y)),
+                           halve4(make_uint2(a.z, a.w), make_uint2(b.z, b.w)));
+        }
     }
 }
 
@@ -634,7 +653,7 @@ __device__ void build_fused(const fg_job &J, int sx0, int sy0, int xr1, int yr1,
     g2 = g0;
     if (J.levels > 1) {
         __syncthreads();
-        halve_tile(smem + T0, smem + T1, st.tw >> 1, st.th >> 1);
+        halve_two(smem + T0, smem + T1, smem + T2, st.tw, st.th, J.levels > 2);
         level_area(J, 1, sx0, sy0, xr1, yr1, g1);
         g1.tbase = T1;
         g1.tx = st.tx >> 1;
@@ -644,8 +663,6 @@ __device__ void build_fused(const fg_job &J, int sx0, int sy0, int xr1, int yr1,
         set_groups(g1);
     }
     if (J.levels > 2) {
-        __syncthreads();
-        halve_tile(smem + T1, smem + T2, st.tw >> 2, st.th >> 2);
         level_area(J, 2, sx0, sy0, xr1, yr1, g2);
         g2.tbase = T2;
         g2.tx = st.tx >> 2;
@@ -794,7 +811,9 @@ __global__ void __launch_bounds__(512) detect_plain_kernel(fg_job J) {
 //     the item after next is drawn before the detection passes of the
 //     current region and resolved after them, so the atomic's round trip,
 //     and any wait for earlier stores, overlaps the passes;
-//   * the job of the next item is looked up while the current one is staged;
+//   * the job of the item after next is looked up while the current region
+//     finishes, and the next item's job is read while waiting for the
+//     previous region's last wave;
 //   * when a region is a single fused sub-tile (and the workgroup has >= 256
 //     threads), the level-0 tile of the next region is loaded into registers
 //     during the passes of the current one.
@@ -816,6 +835,7 @@ __global__ void __launch_bounds__(512) detect_batch_kernel(const fg_job *__restr
     int item = (int)blockIdx.x;
     int next = item + G < total ? item + G : total;
     int jl = item_job[item];
+    int jn = next < total ? (int)item_job[next] : 0;
     int b = 0;
     TileRegs T;
     if (pipe) {
@@ -823,23 +843,21 @@ __global__ void __launch_bounds__(512) detect_batch_kernel(const fg_job *__restr
         if (single_fused(J)) region_prefetch(J, item - J.region_base, T);
     }
     while (item < total) {
-        const fg_job &J = jobs[jl];   // uniform: read through the scalar cache
+        const fg_job &J = jobs[jl];    // uniform: read through the scalar cache
+        const fg_job &Jn = jobs[jn];   // the next item's job, read while waiting below
         const int region = item - J.region_base;
-        const int jn = next < total ? (int)item_job[next] : 0;   // issued early, used after staging
         unsigned ticket = 0;
+        int after;
         if (pipe && single_fused(J)) {
             const Region R = region_of(J, region);
             const Stage st = fused_stage(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1);
             __syncthreads();   // the previous region is done with LDS
             tile_commit(smem + T0, T, st.tw, st.th);
+            if (next < total && single_fused(Jn)) region_prefetch(Jn, next - Jn.region_base, T);
             zero_lds(smem + OFF_M0, OFF_KEYS - OFF_M0);
             keys_clear(keys, R.ncx * R.ncy);
             Geo g0, g1, g2;
             build_fused(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1, st, smem, g0, g1, g2);
-            if (next < total) {
-                const fg_job &Jn = jobs[jn];
-                if (single_fused(Jn)) region_prefetch(Jn, next - Jn.region_base, T);
-            }
             if (threadIdx.x == 0 && next < total) ticket = atomicAdd(&counter[0], 1u);
             run_passes(smem, g0, g1, g2, J.levels, R.P);
             if (threadIdx.x == 0) {
@@ -847,6 +865,7 @@ __global__ void __launch_bounds__(512) detect_batch_kernel(const fg_job *__restr
                 s_next[b] = next < total && cand < (unsigned)total ? (int)cand : total;
             }
             __syncthreads();   // publishes s_next[b]
+            after = s_next[b];
             keys_write(J, R, keys);
         } else {
             if (threadIdx.x == 0 && next < total) ticket = atomicAdd(&counter[0], 1u);
@@ -856,15 +875,13 @@ __global__ void __launch_bounds__(512) detect_batch_kernel(const fg_job *__restr
                 s_next[b] = next < total && cand < (unsigned)total ? (int)cand : total;
             }
             __syncthreads();
-            if (next < total && pipe) {
-                const fg_job &Jn = jobs[jn];
-                if (single_fused(Jn)) region_prefetch(Jn, next - Jn.region_base, T);
-            }
+            after = s_next[b];
+            if (next < total && pipe && single_fused(Jn)) region_prefetch(Jn, next - Jn.region_base, T);
         }
-        const int after = s_next[b];
         item = next;
         next = after;
         jl = jn;
+        jn = after < total ? (int)item_job[after] : 0;
         b ^= 1;
     }
     // Every drawn ticket has been resolved.  The last workgroup out re-arms
