@@ -1,14 +1,16 @@
 """Throughput of the batched FAST pyramid / NMS / cell-select path on one GPU.
 
 Workload: the uneven 64-frame batch (24 x 752x480, 24 x 1280x720, 16 x 640x480,
-3 pyramid levels each, per-frame t, N and cell), resident in HBM, replayed as one
-graph-captured persistent launch per step.  R distinct resident copies of the
-batch are cycled so consecutive steps do not re-read the same bytes from the
-last-level cache.
+3 pyramid levels each, per-frame t, N and cell), resident in HBM, run as one
+persistent launch per step from a resident job table.  R distinct resident
+copies of the batch are cycled so consecutive steps do not re-read the same
+bytes from the last-level cache.
 
 One JSON line is printed: whole-job Mpixel/s (level-0 input pixels), plus the
 plain one-frame-per-launch path on the same frames, per-frame latency of the
-plain path, the HBM roofline of the step and the CPU oracle on a bounded sample.
+plain path on the three single-frame workloads, the serving loop over 32
+camera streams, the HBM roofline of the step and the CPU oracle on a bounded
+sample (one core and frame-parallel).
 """
 from __future__ import annotations
 
@@ -57,11 +59,106 @@ def cpu_baseline(specs, frames, budget_s: float) -> dict:
                       f"{t_total:.1f} s"}
 
 
+def cpu_baseline_parallel(specs, frames, budget_s: float, workers: int) -> dict:
+    """The same oracle, frame-parallel: one frame per worker thread (the C
+    oracle runs outside the interpreter lock), for about budget_s seconds."""
+    import concurrent.futures as cf
+    import oracle
+    state = {"next": 0}
+
+    def one(i):
+        s, img = specs[i % len(specs)], frames[i % len(frames)]
+        oracle.detect_grid(img, s.width, s.levels, s.t, s.n, s.cell)
+        return s.width * s.height
+
+    done_px, nframes = 0, 0
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=workers) as pool:
+        futs = [pool.submit(one, i) for i in range(workers)]
+        state["next"] = workers
+        while futs:
+            f = futs.pop(0)
+            done_px += f.result()
+            nframes += 1
+            if time.perf_counter() - t0 < budget_s:
+                futs.append(pool.submit(one, state["next"]))
+                state["next"] += 1
+    wall = time.perf_counter() - t0
+    return {"value": round(done_px / wall / 1e6, 3), "unit": "Mpixel/s", "cores": workers,
+            "kind": "oracle",
+            "sample": f"{nframes} frames of the 64-frame batch, one frame per thread on "
+                      f"{workers} threads, {wall:.1f} s wall"}
+
+
+def copy_bandwidth(nbytes: int) -> float:
+    """Device-to-device copy rate in GB/s (bytes read + bytes written)."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(7)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / (ms / 1e3) / 1e9
+
+
+def plain_latency(ctx, spec, nframes: int) -> dict:
+    """One frame at a time through the plain path with a host sync after each:
+    upload from pinned memory, detect, download of the cell slots; stage times
+    from device events, total from the host clock."""
+    import torch
+    from paper_2003_13493_amd import fastgrid
+    img = spec.make()
+    pyr = fastgrid.Pyramid(spec.width, spec.height, spec.levels)
+    grid = fastgrid.Grid(spec.width, spec.height, spec.cell)
+    p0 = pyr.dims[0][2]
+    src = np.zeros((spec.height, p0), np.uint8)
+    src[:, :spec.width] = img[:, :spec.width]
+    host_in = torch.from_numpy(src).pin_memory()
+    host_out = torch.empty(grid.tensor.numel(), dtype=torch.uint8, pin_memory=True)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    tot, up, det, down, det_only = [], [], [], [], []
+    for i in range(nframes + 20):
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        pyr.tensors[0].copy_(host_in, non_blocking=True)
+        ev[1].record(stream)
+        ctx.detect(pyr, spec.t, spec.n, spec.cell, grid, stream)
+        ev[2].record(stream)
+        host_out.copy_(grid.tensor, non_blocking=True)
+        ev[3].record(stream)
+        stream.synchronize()
+        t1 = time.perf_counter()
+        if i >= 20:
+            tot.append((t1 - t0) * 1e3)
+            up.append(ev[0].elapsed_time(ev[1]))
+            det.append(ev[1].elapsed_time(ev[2]))
+            down.append(ev[2].elapsed_time(ev[3]))
+    for i in range(nframes + 20):
+        t0 = time.perf_counter()
+        ctx.detect(pyr, spec.t, spec.n, spec.cell, grid, stream)
+        stream.synchronize()
+        if i >= 20:
+            det_only.append((time.perf_counter() - t0) * 1e3)
+    q = lambda a, p: round(float(np.percentile(a, p)), 4)
+    return {"frames": nframes,
+            "upload_detect_download_ms": {"p50": q(tot, 50), "p99": q(tot, 99)},
+            "stage_ms_p50": {"upload": q(up, 50), "detect": q(det, 50), "download": q(down, 50)},
+            "detect_only_ms": {"p50": q(det_only, 50), "p99": q(det_only, 99)}}
+
+
 def kernel_source_hash() -> str:
-    import hashlib
-    path = os.path.join(ROOT, "paper_2003_13493_amd", "csrc", "fastgrid_kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    from paper_2003_13493_amd.profile_tools import kernel_source_hash as h
+    return h()
 
 
 def measured_traffic():
@@ -79,13 +176,15 @@ def measured_traffic():
 
 def serving(ctx, seconds: float) -> dict:
     """32 Poisson camera streams through the continuous-batching server, then
-    the same arrivals served one frame per launch."""
+    the same arrivals served one frame per launch; at the nominal rates, at 4x
+    the rates, and with every frame uploaded from pinned host memory."""
     from paper_2003_13493_amd import serve, synth
     specs = synth.streams32()
     res = {"workload": "32 camera streams: 640x480, 752x480, 1920x1080, 4096x2160 (8 each), "
                        "3-5 levels, per-stream t/N/cell, Poisson 100-1000 frames/s each, "
                        f"{seconds} s of arrivals per mode; results copied to pinned host; "
-                       "the _x4 entries run every stream at 4x its rate"}
+                       "the _x4 entries run every stream at 4x its rate; the +upload entries copy "
+                       "every frame host-to-device before detection (PCIe-inclusive)"}
     srv = serve.Server(ctx, specs, pool_frames=4, slots_per_stream=4, max_batch=64, inflight=4)
     res["offered_mpixel_s"] = round(sum(s.width * s.height * s.rate_fps for s in specs) / 1e6, 1)
     for scale in (1.0, 4.0):
@@ -105,6 +204,22 @@ def serving(ctx, seconds: float) -> dict:
                 f"mean batch {st['mean_batch']}, p50 {st['latency_ms']['p50']} ms "
                 f"p99 {st['latency_ms']['p99']} ms")
     srv.close()
+    srv = serve.Server(ctx, specs, pool_frames=4, slots_per_stream=4, max_batch=64, inflight=4,
+                       upload=True)
+    for mode, batched in (("batched+upload", True), ("plain+upload", False)):
+        srv.run(0.2, seed=99, batched=batched)
+        st = srv.run(seconds, seed=17, batched=batched)
+        st.pop("requests")
+        for k in ("mpixel_s", "wall_s", "mean_batch"):
+            st[k] = round(st[k], 3)
+        st["latency_ms"] = {k: round(v, 4) for k, v in st["latency_ms"].items()}
+        st["latency_ms_by_resolution"] = {
+            r: {k: round(v, 4) for k, v in d.items()}
+            for r, d in st["latency_ms_by_resolution"].items()}
+        res[mode] = st
+        log(f"serving {mode}: {st['frames']} frames in {st['wall_s']} s, {st['mpixel_s']} Mpx/s, "
+            f"p50 {st['latency_ms']['p50']} ms p99 {st['latency_ms']['p99']} ms")
+    srv.close()
     return res
 
 
@@ -120,10 +235,11 @@ def main() -> int:
     ap.add_argument("--instances", type=int, default=8)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--plain-latency-frames", type=int, default=300)
+    ap.add_argument("--plain-latency-frames", type=int, default=1000)
+    ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run device-to-device copies of this size (counter calibration)")
-    ap.add_argument("--serve-seconds", type=float, default=2.0,
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="seconds of Poisson arrivals per serving mode (0 skips serving)")
     ap.add_argument("--launch", type=str, default="",
                     help="region,block,blocks_per_cu launch shape (default: library default)")
@@ -227,20 +343,13 @@ def main() -> int:
     plain_ms = e0.elapsed_time(e1) / reps
     plain_value = px_per_step / (plain_ms / 1e3) / 1e6
 
-    # ---- plain per-frame latency (sync after each frame), 752x480 L=3 frame
-    lspec = synth.PLAIN_752
-    limg = lspec.make()
-    lp = fastgrid.Pyramid(lspec.width, lspec.height, lspec.levels)
-    lp.upload(limg)
-    lg = fastgrid.Grid(lspec.width, lspec.height, lspec.cell)
-    lat = []
-    for i in range(args.plain_latency_frames + 20):
-        t0 = time.perf_counter()
-        ctx.detect(lp, lspec.t, lspec.n, lspec.cell, lg, stream)
-        stream.synchronize()
-        if i >= 20:
-            lat.append((time.perf_counter() - t0) * 1e3)
-    lat = np.array(lat)
+    # ---- plain per-frame latency (sync after each frame) on the three single-frame workloads
+    latency = {}
+    for name, lspec in (("320x240_L1", synth.PLAIN_320), ("752x480_L3", synth.PLAIN_752),
+                        ("1920x1080_L4", synth.PLAIN_1080)):
+        latency[name] = plain_latency(ctx, lspec, args.plain_latency_frames)
+        log(f"plain latency {name}: {latency[name]['upload_detect_download_ms']}")
+    copy_gbs = copy_bandwidth(1 << 30)
 
     achieved = bytes_per_step / (ms_per_step / 1e3) / 1e9
     out = {
@@ -260,7 +369,7 @@ def main() -> int:
         "config": {
             "workload": "batch64: 24x752x480 + 24x1280x720 + 16x640x480, 3 levels, per-frame "
                         "t in {8,10,15,20}, N in {9,10,12}, cell in {16,32,64}; one "
-                        "graph-captured persistent launch per step",
+                        "persistent launch per step from a resident job table",
             "frames_per_step": len(specs0),
             "level0_pixels_per_step": px_per_step,
             "resident_instances": args.instances,
@@ -271,6 +380,8 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "measured_copy_gbs": round(copy_gbs, 1),
+            "frac_of_measured_copy": round(achieved / copy_gbs, 4),
             "traffic": measured_traffic(),
             "algorithmic_bytes_per_launch": bytes_per_step,
         },
@@ -284,18 +395,20 @@ def main() -> int:
             "batched_speedup": round(value / plain_value, 3),
         },
         "latency_ms": {
-            "workload": "plain path, one 752x480 L=3 frame, host sync after each",
-            "p50": round(float(np.percentile(lat, 50)), 4),
-            "p99": round(float(np.percentile(lat, 99)), 4),
+            "workload": "plain path, one frame at a time with a host sync after each: upload from "
+                        "pinned memory, detect, download of the cell slots",
+            **latency,
         },
         "wall_s_timed": round(t_wall, 3),
     }
-    log(f"plain: {plain_ms:.4f} ms per 64 frames; latency p50 {np.percentile(lat, 50):.4f} ms")
+    log(f"plain: {plain_ms:.4f} ms per 64 frames")
     if args.serve_seconds > 0:
         out["serving"] = serving(ctx, args.serve_seconds)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(frames0[0], frames0[1], args.cpu_budget)
         out["cpu_baseline"]["sample"] += f"; host: {os.cpu_count()} logical CPUs"
+        out["cpu_baseline_all_cores"] = cpu_baseline_parallel(frames0[0], frames0[1],
+                                                              min(args.cpu_budget, 8.0), args.cpu_workers)
     if args.copy_probe_mib:
         nbytes = args.copy_probe_mib << 20
         src = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")

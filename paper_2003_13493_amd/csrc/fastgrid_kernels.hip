@@ -10,29 +10,28 @@
 // once, levels 1.. written once).  Deeper pyramids are built by a separate
 // kernel and each level's sub-tile is loaded with a 4-pixel halo.
 //
-// Detection inside a sub-tile is split into row strips (<= 16 rows plus a
-// 1-row ring above and below), one strip at a time per wave, with no
-// workgroup barrier: every strip computes the scores of its own ring rows, so
-// a wave never waits for another.  Per strip:
+// Detection of a sub-tile scores every pixel of its area plus a 1-pixel ring
+// at every level:
 //
-//   P1 compass test, all pixels, 8 per lane in packed 16-bit lanes.  An arc of
-//      N circle pixels contains floor(N/4) consecutive compass points (circle
-//      indices 0, 4, 8, 12) of its label.  Result: one flag bit per pixel.
-//   P2 compaction of the survivors into a wave-private LDS list (DPP prefix
-//      scan of per-lane counts).
+//   P1 compass test, 8 pixels per lane in packed 16-bit lanes.  An arc of N
+//      circle pixels contains floor(N/4) consecutive compass points (circle
+//      indices 0, 4, 8, 12) of its label.  The 8-pixel groups of all levels
+//      are dealt to the waves round-robin in rounds of 64.
+//   P2 compaction of the survivors into a wave-private LDS list (ballot +
+//      mbcnt over groups, then a DPP prefix scan over pixels).
 //   P3 8-point test, one survivor per lane: the arc also contains floor(N/2)
-//      consecutive even circle points of its label.  In-place compaction
-//      (ballot + mbcnt).
+//      consecutive even circle points of its label.  In-place compaction.
 //   P4 full segment test and score (Section II-D, Eq. (1)) into the level's
-//      score map (a 1-pixel ring around the sub-tile, shared by the strips).
-//   P5 3x3 NMS (Section I-B, n=1) of the strip's own rows and an LDS atomicMax
-//      of a 32-bit key per cell: (score << 19) | ((7-level) << 16) |
-//      (0xFFFF - row-major index inside the cell), which orders candidates by
-//      (score desc, level asc, index asc), so the cell's answer does not
-//      depend on thread order.
+//      score map (the sub-tile area plus its ring).
+//   P5 after one workgroup barrier, 3x3 NMS (Section I-B, n=1) of the
+//      sub-tile's own pixels and an LDS atomicMax of a 32-bit key per cell:
+//      (score << 19) | ((7-level) << 16) | (0xFFFF - row-major index inside
+//      the cell), which orders candidates by (score desc, level asc, index
+//      asc), so the cell's answer does not depend on thread order.
 //
-// Both filters are necessary conditions of the segment test, so a pixel they
-// reject has score 0; the cascade never changes a result.
+// P1-P4 need no workgroup barrier.  Both filters are necessary conditions of
+// the segment test, so a pixel they reject has score 0; the cascade never
+// changes a result.
 #include "fg_internal.h"
 
 namespace {

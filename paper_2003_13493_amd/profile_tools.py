@@ -1,12 +1,15 @@
 """Summaries of rocprofv3 CSV output for the committed profile records.
 
-    python -m paper_2003_13493_amd.profile_tools trace  <kernel_stats.csv>
-    python -m paper_2003_13493_amd.profile_tools traffic <fetch_dir> <write_dir> <copy_bytes>
+    python -m paper_2003_13493_amd.profile_tools trace    <kernel_stats.csv> [out.md "command"]
+    python -m paper_2003_13493_amd.profile_tools traffic  <fetch_dir> <write_dir> <copy_bytes> [out.json "cmd" ...]
+    python -m paper_2003_13493_amd.profile_tools counters <pmc_dir> [out.md "command"]
 
 `traffic` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch, two separate
 --pmc runs) of the batched detect kernel into HBM bytes per launch.  Each
 counter is scaled by the ratio between the bytes a plain device-to-device copy
-of known size must move and what the same counter reads for that copy.
+of known size must move and what the same counter reads for that copy (the
+largest copy dispatch of the run, which must be the copy of copy_bytes).
+`counters` averages SQ_* counters per dispatch of the batched kernel.
 """
 from __future__ import annotations
 
@@ -61,9 +64,73 @@ def trace(stats_csv: str) -> list[dict]:
                  "total_ns": int(float(r["TotalDurationNs"]))} for r in csv.DictReader(f)]
 
 
+def kernel_source_hash() -> str:
+    """sha256[:16] of the kernel source with comments and blank space removed,
+    so that a record stays valid across comment-only edits."""
+    import hashlib
+    import re
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "fastgrid_kernels.hip")
+    with open(path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    text = "\n".join(line.strip() for line in text.splitlines() if line.strip())
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    for key in ("detect_batch_kernel", "detect_plain_kernel", "pyr_batch_kernel", "pyr_kernel"):
+        if key + "(" in name:
+            return key
+    if "FillFunctor" in name:
+        return "torch fill (harness)"
+    return name[:60]
+
+
+def trace_md(stats_csv: str, command: str) -> str:
+    rows = trace(stats_csv)
+    lines = ["| kernel | calls | average ns | total ns |", "|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| {short_name(r['name'])} | {r['calls']} | {r['avg_ns']:.0f} | {r['total_ns']} |")
+    return "\n".join([
+        "# Kernel trace: batched detect kernel on the 64-frame batch (one MI355X)", "",
+        "Command (repo root):", "", "    " + command, "",
+        f"Summary: `python -m paper_2003_13493_amd.profile_tools trace {stats_csv}`.",
+        "detect_batch_kernel is one persistent launch over the whole 64-frame batch (pyramid levels 1-2",
+        "are built inside it); detect_plain_kernel is the plain path, one launch per frame.",
+        f"Kernel source hash (sha256[:16] of the source without comments) = {kernel_source_hash()}.", "", *lines, ""])
+
+
+def counters(pmc_dir: str, name_part: str = "detect_batch_kernel") -> dict:
+    rows = _rows(pmc_dir)
+    names = sorted({r["Counter_Name"] for r in rows})
+    return {n: statistics.median(per_dispatch(rows, n, name_part)) for n in names
+            if per_dispatch(rows, n, name_part)}
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
+        if len(sys.argv) > 3:
+            with open(sys.argv[3], "w") as f:
+                f.write(trace_md(sys.argv[2], sys.argv[4]))
         for r in trace(sys.argv[2]):
             print(f"{r['calls']:6d} {r['avg_ns']:12.0f} ns  {r['name'][:110]}")
     elif sys.argv[1] == "traffic":
-        print(json.dumps(traffic(sys.argv[2], sys.argv[3], int(sys.argv[4])), indent=1))
+        rec = traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]))
+        if len(sys.argv) > 5:
+            rec["kernel_source_sha256_16"] = kernel_source_hash()
+            rec["commands"] = sys.argv[6:]
+            with open(sys.argv[5], "w") as f:
+                json.dump(rec, f, indent=1)
+        print(json.dumps(rec, indent=1))
+    elif sys.argv[1] == "counters":
+        rec = counters(sys.argv[2])
+        if len(sys.argv) > 3:
+            lines = ["| counter | per dispatch (median) |", "|---|---|"]
+            lines += [f"| {k} | {v:.0f} |" for k, v in rec.items()]
+            with open(sys.argv[3], "w") as f:
+                f.write("\n".join(["# SQ counters: batched detect kernel on the 64-frame batch", "",
+                                    "Command (repo root):", "", "    " + sys.argv[4], "",
+                                    f"Kernel source hash (sha256[:16] of the source without comments) = {kernel_source_hash()}.", "",
+                                    *lines, ""]))
+        print(json.dumps(rec, indent=1))

@@ -39,12 +39,13 @@ def alone(ctx, spec, img):
     return g.fetch()
 
 
-@pytest.mark.parametrize("batched", [True, False])
-def test_each_result_same_alone_and_in_mix(ctx, batched):
+@pytest.mark.parametrize("batched,upload", [(True, False), (False, False), (True, True)],
+                         ids=["batched", "plain", "batched_upload"])
+def test_each_result_same_alone_and_in_mix(ctx, batched, upload):
     specs = small_streams()
     srv = serve.Server(ctx, specs, pool_frames=2, slots_per_stream=3, max_batch=16, inflight=3,
-                       keep_results=True)
-    print(f"case serve batched={batched}", flush=True)
+                       keep_results=True, upload=upload)
+    print(f"case serve batched={batched} upload={upload}", flush=True)
     stats = srv.run(0.4, seed=11, batched=batched)
     assert stats["frames"] == stats["offered_frames"] > 50
     assert stats["latency_ms"]["p50"] is not None

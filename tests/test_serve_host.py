@@ -39,6 +39,8 @@ def test_resident_bytes_counts_pool_slots_and_grid():
     upper = 240 * 320 + 120 * 192
     cells = 20 * 15
     assert b == 2 * lvl0 + 3 * (upper + 8 * cells)
+    # frames uploaded per request: a level-0 plane per slot instead of the pool
+    assert serve.resident_bytes(s, 2, 3, upload=True) == 3 * (lvl0 + upper + 8 * cells)
 
 
 def test_stream_workload_recipe():
