@@ -804,7 +804,7 @@ __global__ void __launch_bounds__(512) detect_plain_kernel(fg_job J) {
 }
 
 // Persistent batched detector.  Work items are regions of all jobs
-// (item_job maps an item to its job).  Latencies are taken off the critical
+// (items[] gives each one's job and region).  Latencies are taken off the critical
 // path by working ahead:
 //   * the first two items of a workgroup are fixed, and the queue ticket of
 //     the item after next is drawn before the detection passes of the
@@ -817,7 +817,7 @@ __global__ void __launch_bounds__(512) detect_plain_kernel(fg_job J) {
 //     threads), the level-0 tile of the next region is loaded into registers
 //     during the passes of the current one.
 __global__ void __launch_bounds__(512) detect_batch_kernel(const fg_job *__restrict__ jobs,
-                                                           const uint16_t *__restrict__ item_job,
+                                                           const fg_item *__restrict__ items,
                                                            int total, unsigned *counter) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     // Work items: workgroup g starts with items g and g + G (G blocks, at most
@@ -833,18 +833,18 @@ __global__ void __launch_bounds__(512) detect_batch_kernel(const fg_job *__restr
     const int G = (int)gridDim.x;
     int item = (int)blockIdx.x;
     int next = item + G < total ? item + G : total;
-    int jl = item_job[item];
-    int jn = next < total ? (int)item_job[next] : 0;
+    fg_item il = items[item];
+    fg_item in = next < total ? items[next] : fg_item{0u, 0u};
     int b = 0;
     TileRegs T;
     if (pipe) {
-        const fg_job &J = jobs[jl];
-        if (single_fused(J)) region_prefetch(J, item - J.region_base, T);
+        const fg_job &J = jobs[il.job];
+        if (single_fused(J)) region_prefetch(J, (int)il.region, T);
     }
     while (item < total) {
-        const fg_job &J = jobs[jl];    // uniform: read through the scalar cache
-        const fg_job &Jn = jobs[jn];   // the next item's job, read while waiting below
-        const int region = item - J.region_base;
+        const fg_job &J = jobs[il.job];    // uniform: read through the scalar cache
+        const fg_job &Jn = jobs[in.job];   // the next item's job, read while waiting below
+        const int region = (int)il.region;
         unsigned ticket = 0;
         int after;
         if (pipe && single_fused(J)) {
@@ -852,7 +852,7 @@ __global__ void __launch_bounds__(512) detect_batch_kernel(const fg_job *__restr
             const Stage st = fused_stage(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1);
             __syncthreads();   // the previous region is done with LDS
             tile_commit(smem + T0, T, st.tw, st.th);
-            if (next < total && single_fused(Jn)) region_prefetch(Jn, next - Jn.region_base, T);
+            if (next < total && single_fused(Jn)) region_prefetch(Jn, (int)in.region, T);
             zero_lds(smem + OFF_M0, OFF_KEYS - OFF_M0);
             keys_clear(keys, R.ncx * R.ncy);
             Geo g0, g1, g2;
@@ -875,12 +875,12 @@ __global__ void __launch_bounds__(512) detect_batch_kernel(const fg_job *__restr
             }
             __syncthreads();
             after = s_next[b];
-            if (next < total && pipe && single_fused(Jn)) region_prefetch(Jn, next - Jn.region_base, T);
+            if (next < total && pipe && single_fused(Jn)) region_prefetch(Jn, (int)in.region, T);
         }
         item = next;
         next = after;
-        jl = jn;
-        jn = after < total ? (int)item_job[after] : 0;
+        il = in;
+        in = after < total ? items[after] : fg_item{0u, 0u};
         b ^= 1;
     }
     // Every drawn ticket has been resolved.  The last workgroup out re-arms
@@ -968,7 +968,7 @@ hipError_t fg_launch_plain(const fg_job &j, const fg_launch &L, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t fg_launch_batch(const fg_job *jobs_dev, const uint16_t *item_job, int njobs, int total,
+hipError_t fg_launch_batch(const fg_job *jobs_dev, const fg_item *items, int njobs, int total,
                            int max_levels, int max_w1, int max_h1, unsigned *counter,
                            const fg_launch &L, hipStream_t s) {
     int mw = max_w1, mh = max_h1;
@@ -984,6 +984,6 @@ hipError_t fg_launch_batch(const fg_job *jobs_dev, const uint16_t *item_job, int
     if (blocks > total) blocks = total;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(detect_batch_kernel, dim3(blocks), dim3(L.block), fg_smem_bytes(L.block), s,
-                       jobs_dev, item_job, total, counter);
+                       jobs_dev, items, total, counter);
     return hipGetLastError();
 }

@@ -26,8 +26,8 @@ struct TableSlot {
     fg_job *host = nullptr;        // pinned staging copy
     fg_job *dev = nullptr;
     unsigned *counter = nullptr;   // persistent-queue counters (FG_COUNTER_WORDS)
-    uint16_t *items_host = nullptr;   // pinned item -> job map
-    uint16_t *items_dev = nullptr;
+    fg_item *items_host = nullptr;   // pinned work-item table
+    fg_item *items_dev = nullptr;
     int items_cap = 0;
     uint64_t ticket = 0;           // last submission that used this slot
 };
@@ -35,7 +35,7 @@ struct TableSlot {
 struct Plan {
     bool live = false;
     fg_job *dev = nullptr;
-    uint16_t *items = nullptr;
+    fg_item *items = nullptr;
     unsigned *counter = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -189,11 +189,22 @@ int build_table(fast_ctx *c, const fast_job *jobs, int njobs, fg_job *table, int
     return FAST_OK;
 }
 
-// items[i] = the job that owns work item i (regions in job order).
-void fill_items(const fg_job *table, int njobs, uint16_t *items) {
-    for (int j = 0; j < njobs; ++j) {
-        const int n = table[j].rx * table[j].ry;
-        for (int r = 0; r < n; ++r) items[table[j].region_base + r] = (uint16_t)j;
+// The work items (job, region) of a batch.  Whole regions come first and the
+// regions clipped at a frame's right or bottom edge last, each group in job
+// and region order: the cheap items end the queue, so the persistent
+// workgroups run out of work closer together.
+void fill_items(const fg_job *table, int njobs, fg_item *items) {
+    int n = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int j = 0; j < njobs; ++j) {
+            const fg_job &J = table[j];
+            const int side = J.rcells * J.cell;
+            for (int r = 0; r < J.rx * J.ry; ++r) {
+                const int x0 = (r % J.rx) * side, y0 = (r / J.rx) * side;
+                const bool whole = x0 + side <= J.w[0] && y0 + side <= J.h[0];
+                if (whole == (pass == 0)) items[n++] = fg_item{(uint32_t)j, (uint32_t)r};
+            }
+        }
     }
 }
 
@@ -369,9 +380,9 @@ FG_API int fast_submit(fast_ctx *c, const fast_job *jobs, int njobs, void *strea
         S.items_dev = nullptr;
         S.items_cap = 0;
         const int cap = total > 65536 ? total : 65536;
-        hipError_t e = hipHostMalloc((void **)&S.items_host, sizeof(uint16_t) * cap, hipHostMallocDefault);
+        hipError_t e = hipHostMalloc((void **)&S.items_host, sizeof(fg_item) * cap, hipHostMallocDefault);
         if (e != hipSuccess) { S.items_host = nullptr; return hip_fail(c, e, "hipHostMalloc item map"); }
-        e = hipMalloc((void **)&S.items_dev, sizeof(uint16_t) * cap);
+        e = hipMalloc((void **)&S.items_dev, sizeof(fg_item) * cap);
         if (e != hipSuccess) { S.items_dev = nullptr; return hip_fail(c, e, "hipMalloc item map"); }
         S.items_cap = cap;
     }
@@ -379,7 +390,7 @@ FG_API int fast_submit(fast_ctx *c, const fast_job *jobs, int njobs, void *strea
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(S.dev, S.host, sizeof(fg_job) * njobs, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(c, e, "job table upload");
-    e = hipMemcpyAsync(S.items_dev, S.items_host, sizeof(uint16_t) * total, hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(S.items_dev, S.items_host, sizeof(fg_item) * total, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(c, e, "item map upload");
     e = fg_launch_batch(S.dev, S.items_dev, njobs, total, max_levels, mw1, mh1, S.counter, c->launch, s);
     if (e != hipSuccess) return hip_fail(c, e, "batch launch");
@@ -426,11 +437,11 @@ FG_API int fast_plan_create(fast_ctx *c, const fast_job *jobs, int njobs, int fl
     p.max_levels = max_levels;
     p.mw1 = mw1;
     p.mh1 = mh1;
-    std::vector<uint16_t> items((size_t)total);
+    std::vector<fg_item> items((size_t)total);
     fill_items(table.data(), njobs, items.data());
     hipError_t e = hipMalloc((void **)&p.dev, sizeof(fg_job) * njobs);
     if (e != hipSuccess) return hip_fail(c, e, "hipMalloc plan table");
-    e = hipMalloc((void **)&p.items, sizeof(uint16_t) * total);
+    e = hipMalloc((void **)&p.items, sizeof(fg_item) * total);
     if (e != hipSuccess) { (void)hipFree(p.dev); return hip_fail(c, e, "hipMalloc plan item map"); }
     e = hipMalloc((void **)&p.counter, FG_COUNTER_WORDS * sizeof(unsigned));
     if (e != hipSuccess) {
@@ -439,7 +450,7 @@ FG_API int fast_plan_create(fast_ctx *c, const fast_job *jobs, int njobs, int fl
         return hip_fail(c, e, "hipMalloc plan counter");
     }
     e = hipMemcpy(p.dev, table.data(), sizeof(fg_job) * njobs, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(p.items, items.data(), sizeof(uint16_t) * total, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p.items, items.data(), sizeof(fg_item) * total, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p.counter, 0, FG_COUNTER_WORDS * sizeof(unsigned));
     if (e == hipSuccess && (flags & FAST_PLAN_GRAPH)) {
         if (!c->capture_stream) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);

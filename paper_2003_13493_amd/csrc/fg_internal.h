@@ -45,10 +45,17 @@ hipError_t fg_launch_pyramid(const fg_job &j, hipStream_t s);
 // the exit count (the rest is padding).
 constexpr int FG_COUNTER_WORDS = 16;
 
+// One work item of the batched kernel: a region of a job.
+struct fg_item {
+    uint32_t job;
+    uint32_t region;
+};
+
 // Batched path: `jobs_dev` is a device copy of njobs jobs whose region_base
-// fields are prefix sums; `total` is the number of work items and
-// `item_job[i]` the job of item i; `counter` holds FG_COUNTER_WORDS
-// zero-initialised words that the kernel re-arms itself on exit.
-hipError_t fg_launch_batch(const fg_job *jobs_dev, const uint16_t *item_job, int njobs, int total,
+// fields are prefix sums; `total` is the number of work items and `items`
+// lists them (every region of every job once, in any order); `counter` holds
+// FG_COUNTER_WORDS zero-initialised words that the kernel re-arms itself on
+// exit.
+hipError_t fg_launch_batch(const fg_job *jobs_dev, const fg_item *items, int njobs, int total,
                            int max_levels, int max_w1, int max_h1, unsigned *counter,
                            const fg_launch &L, hipStream_t s);
