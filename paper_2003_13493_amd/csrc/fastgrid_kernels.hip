@@ -269,8 +269,11 @@ __device__ int collect(const uint8_t *smem, const Seg &s0, const Seg &s1, const 
     const int lane = lane_id(), wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int total = s0.n + s1.n + s2.n;
     const int b1 = s0.n, b2 = s0.n + s1.n;
-    const float inv0 = 1.0f / (float)max(s0.ppr, 1), inv1 = 1.0f / (float)max(s1.ppr, 1),
-                inv2 = 1.0f / (float)max(s2.ppr, 1);
+    // row = floor((local + 0.5) / ppr), exact with the approximate reciprocal
+    // since local < 1024 and ppr <= 9
+    const float inv0 = __builtin_amdgcn_rcpf((float)max(s0.ppr, 1)),
+                inv1 = __builtin_amdgcn_rcpf((float)max(s1.ppr, 1)),
+                inv2 = __builtin_amdgcn_rcpf((float)max(s2.ppr, 1));
     const s16x2 T1 = {(short)(t + 1), (short)(t + 1)};
     int nb = 0;
     for (int i0 = wave * 64; i0 < total; i0 += nwaves * 64) {
@@ -402,10 +405,11 @@ __device__ __forceinline__ void tile_rc(uint32_t off, int &row, int &col) {
 // Per-level constants for mapping an entry to its score map and cell.
 struct LevelMap {
     int mp, mbias;       // map index = row * mp + col + mbias (row, col in the tile band)
-    int rlo, rhi;        // band rows this pass owns for NMS: [rlo, rhi)
+    int rlo, rhi;        // band rows of the sub-tile area: [rlo, rhi)
     int clo, chi;        // band columns of the sub-tile area: [clo, chi)
     int xo, yo;          // cell-relative position = (col + xo, row + yo)
     int cw;              // cell side at this level
+    float inv_cw;        // ~1/cw: floor((v + 0.5) * inv_cw) = v / cw for 0 <= v < 2^12
 };
 
 __device__ __forceinline__ LevelMap level_map(const Geo &g, int band_row, int band_col, int ra,
@@ -421,6 +425,7 @@ __device__ __forceinline__ LevelMap level_map(const Geo &g, int band_row, int ba
     m.xo = xbias - (P.rx0 >> g.k);
     m.yo = ybias - (P.ry0 >> g.k);
     m.cw = P.cell >> g.k;
+    m.inv_cw = __builtin_amdgcn_rcpf((float)max(m.cw, 1));
     return m;
 }
 
@@ -487,7 +492,10 @@ __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Ge
         const int cw = sel3(l, m0.cw, m1.cw, m2.cw);
         const int ox = col + sel3(l, m0.xo, m1.xo, m2.xo);
         const int oy = row + sel3(l, m0.yo, m1.yo, m2.yo);
-        const int cy = oy / cw, cx = ox / cw;
+        // exact: v + 0.5 is at least 0.5 / cw from a multiple of cw, far above
+        // the error of the approximate reciprocal for v < 2^12
+        const float inv = l == 0 ? m0.inv_cw : (l == 1 ? m1.inv_cw : m2.inv_cw);
+        const int cy = (int)(((float)oy + 0.5f) * inv), cx = (int)(((float)ox + 0.5f) * inv);
         const uint32_t local = (uint32_t)((oy - cy * cw) * cw + (ox - cx * cw));
         const uint32_t key = (s << 19) | ((uint32_t)(7 - (g0.k + l)) << 16) | (0xFFFFu - local);
         atomicMax(&keys[cy * P.ncx + cx], key);
