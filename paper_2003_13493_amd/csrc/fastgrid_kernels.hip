@@ -37,7 +37,7 @@
 namespace {
 
 constexpr int SUB = 64;                 // sub-tile side at level 0
-constexpr int MAX_FUSED = 3;            // levels built in LDS from one load
+constexpr int MAX_FUSED = FG_MAX_FUSED;   // levels built in LDS from one load
 
 // All level tiles share one LDS row pitch, so circle offsets are constants.
 // Band A (rows 0..95): level 0 of a fused sub-tile, or the current level of an
@@ -629,14 +629,19 @@ __device__ __forceinline__ void level_area(const fg_job &J, int k, int sx0, int 
     g.ey = min(min((sy0 + SUB) >> k, yr1 >> k), g.H);
 }
 
-// Level-0 tile of a fused sub-tile: the sub-tile plus a 4*2^(L-1) halo, with
-// the left edge rounded down to 16 pixels.
+// Levels 0 .. fused_levels(J)-1 are detected from one level-0 load; levels
+// beyond (jobs with more than MAX_FUSED levels) are detected afterwards by
+// the upper-level pass.
+__device__ __forceinline__ int fused_levels(const fg_job &J) { return min(J.levels, MAX_FUSED); }
+
+// Level-0 tile of a fused sub-tile: the sub-tile plus a 4*2^(F-1) halo (F
+// fused levels), with the left edge rounded down to 16 pixels.
 struct Stage {
     int tx, ty, tw, th;
 };
 
 __device__ __forceinline__ Stage fused_stage(const fg_job &J, int sx0, int sy0, int xr1, int yr1) {
-    const int H0 = 4 << (J.levels - 1);
+    const int H0 = 4 << (fused_levels(J) - 1);
     Stage st;
     st.tx = (sx0 - H0) & ~15;
     st.ty = sy0 - H0;
@@ -658,9 +663,10 @@ __device__ void build_fused(const fg_job &J, int sx0, int sy0, int xr1, int yr1,
     set_groups(g0);
     g1 = g0;
     g2 = g0;
-    if (J.levels > 1) {
+    const int nl = fused_levels(J);
+    if (nl > 1) {
         __syncthreads();
-        halve_two(smem + T0, smem + T1, smem + T2, st.tw, st.th, J.levels > 2);
+        halve_two(smem + T0, smem + T1, smem + T2, st.tw, st.th, nl > 2);
         level_area(J, 1, sx0, sy0, xr1, yr1, g1);
         g1.tbase = T1;
         g1.tx = st.tx >> 1;
@@ -669,7 +675,7 @@ __device__ void build_fused(const fg_job &J, int sx0, int sy0, int xr1, int yr1,
         g1.mp = M1_P;
         set_groups(g1);
     }
-    if (J.levels > 2) {
+    if (nl > 2) {
         level_area(J, 2, sx0, sy0, xr1, yr1, g2);
         g2.tbase = T2;
         g2.tx = st.tx >> 2;
@@ -679,44 +685,47 @@ __device__ void build_fused(const fg_job &J, int sx0, int sy0, int xr1, int yr1,
         set_groups(g2);
     }
     __syncthreads();
-    if (J.levels > 1 && has_area(g1))
+    if (nl > 1 && has_area(g1))
         store_level(smem + T1, g1.tx, g1.ty, J.lvl[1], J.pitch[1], g1.sx, g1.sy, g1.ex, g1.ey);
-    if (J.levels > 2 && has_area(g2))
+    if (nl > 2 && has_area(g2))
         store_level(smem + T2, g2.tx, g2.ty, J.lvl[2], J.pitch[2], g2.sx, g2.sy, g2.ex, g2.ey);
 }
 
-// One level-0 sub-tile of a region: stage, detect, fold into keys.
+// One level-0 sub-tile of a region: stage levels 0 .. F-1, detect, fold into
+// keys.
 __device__ void process_subtile(const fg_job &J, int sx0, int sy0, int xr1, int yr1,
                                 const Params &P, uint8_t *smem) {
-    if (J.levels <= MAX_FUSED) {
-        // one load with a 4*2^(L-1) halo; levels 1.. built in LDS
-        const Stage st = fused_stage(J, sx0, sy0, xr1, yr1);
+    // one load with a 4*2^(F-1) halo; levels 1 .. F-1 built in LDS
+    const Stage st = fused_stage(J, sx0, sy0, xr1, yr1);
+    __syncthreads();
+    load_tile(smem + T0, J.lvl[0], J.h[0], J.pitch[0], st.tx, st.ty, st.tw, st.th);
+    zero_lds(smem + OFF_M0, OFF_KEYS - OFF_M0);
+    Geo g0, g1, g2;
+    build_fused(J, sx0, sy0, xr1, yr1, st, smem, g0, g1, g2);
+    run_passes(smem, g0, g1, g2, fused_levels(J), P);
+}
+
+// Levels MAX_FUSED .. L-1 of one level-0 sub-tile (already built in their
+// planes): one level at a time, loaded with a 4-pixel halo.
+__device__ void process_subtile_upper(const fg_job &J, int sx0, int sy0, int xr1, int yr1,
+                                      const Params &P, uint8_t *smem) {
+    for (int k = MAX_FUSED; k < J.levels; ++k) {
+        Geo g;
+        level_area(J, k, sx0, sy0, xr1, yr1, g);
+        if (!has_area(g)) continue;
+        const int tx = (g.sx - 4) & ~15, ty = g.sy - 4;
+        const int tw = ((g.ex + 4 + 15) & ~15) - tx, th = g.ey + 4 - ty;
         __syncthreads();
-        load_tile(smem + T0, J.lvl[0], J.h[0], J.pitch[0], st.tx, st.ty, st.tw, st.th);
-        zero_lds(smem + OFF_M0, OFF_KEYS - OFF_M0);
-        Geo g0, g1, g2;
-        build_fused(J, sx0, sy0, xr1, yr1, st, smem, g0, g1, g2);
-        run_passes(smem, g0, g1, g2, J.levels, P);
-    } else {
-        // levels already built: one level at a time with a 4-pixel halo
-        for (int k = 0; k < J.levels; ++k) {
-            Geo g;
-            level_area(J, k, sx0, sy0, xr1, yr1, g);
-            if (!has_area(g)) continue;
-            const int tx = (g.sx - 4) & ~15, ty = g.sy - 4;
-            const int tw = ((g.ex + 4 + 15) & ~15) - tx, th = g.ey + 4 - ty;
-            __syncthreads();
-            load_tile(smem + T0, J.lvl[k], g.H, J.pitch[k], tx, ty, tw, th);
-            zero_lds(smem + OFF_M0, (M0_ROWS * M0_P * 2 + 15) & ~15);
-            __syncthreads();
-            g.tbase = T0;
-            g.tx = tx;
-            g.ty = ty;
-            g.moff = OFF_M0;
-            g.mp = M0_P;
-            set_groups(g);
-            run_passes(smem, g, g, g, 1, P);
-        }
+        load_tile(smem + T0, J.lvl[k], g.H, J.pitch[k], tx, ty, tw, th);
+        zero_lds(smem + OFF_M0, (M0_ROWS * M0_P * 2 + 15) & ~15);
+        __syncthreads();
+        g.tbase = T0;
+        g.tx = tx;
+        g.ty = ty;
+        g.moff = OFF_M0;
+        g.mp = M0_P;
+        set_groups(g);
+        run_passes(smem, g, g, g, 1, P);
     }
 }
 
@@ -784,11 +793,41 @@ __device__ void detect_region(const fg_job &J, int region, uint8_t *smem) {
     keys_write(J, R, keys);
 }
 
-// A region is one fused sub-tile when its pyramid is built in LDS and it is
-// at most one sub-tile wide and tall.
-__device__ __forceinline__ bool single_fused(const fg_job &J) {
-    return J.levels <= MAX_FUSED && J.rcells * J.cell <= SUB;
+// Cell keys of a region from the slots an earlier pass wrote (the inverse
+// of keys_write).
+__device__ void keys_from_slots(const fg_job &J, const Region &R, uint32_t *keys) {
+    for (int i = threadIdx.x; i < R.ncx * R.ncy; i += blockDim.x) {
+        const int cx = R.rxi * J.rcells + i % R.ncx, cy = R.ryi * J.rcells + i / R.ncx;
+        const uint64_t f = gload<uint64_t>(J.out + (size_t)cy * J.gw + cx);
+        const uint32_t score = (uint32_t)(f >> 32) & 0xFFFFu;
+        uint32_t key = 0;
+        if (score) {
+            const int level = (int)((f >> 48) & 0xFFu);
+            const int cw = J.cell >> level;
+            const int lx = (int)(f & 0xFFFFu) - ((cx * J.cell) >> level);
+            const int ly = (int)((f >> 16) & 0xFFFFu) - ((cy * J.cell) >> level);
+            key = (score << 19) | ((uint32_t)(7 - level) << 16) | (0xFFFFu - (uint32_t)(ly * cw + lx));
+        }
+        keys[i] = key;
+    }
 }
+
+// Levels MAX_FUSED .. L-1 of a region, merged into the slots of levels below.
+__device__ void detect_region_upper(const fg_job &J, int region, uint8_t *smem) {
+    const Region R = region_of(J, region);
+    uint32_t *keys = (uint32_t *)(smem + OFF_KEYS);
+    __syncthreads();
+    keys_from_slots(J, R, keys);
+    for (int sy0 = R.P.ry0; sy0 < R.yr1; sy0 += SUB)
+        for (int sx0 = R.P.rx0; sx0 < R.xr1; sx0 += SUB)
+            process_subtile_upper(J, sx0, sy0, R.xr1, R.yr1, R.P, smem);
+    __syncthreads();
+    keys_write(J, R, keys);
+}
+
+// A region is one fused sub-tile when it is at most one sub-tile wide and
+// tall.
+__device__ __forceinline__ bool single_fused(const fg_job &J) { return J.rcells * J.cell <= SUB; }
 
 // Issue the level-0 tile loads of a single-fused-sub-tile region.
 __device__ __forceinline__ void region_prefetch(const fg_job &J, int region, TileRegs &T) {
@@ -809,6 +848,20 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
 __global__ void __launch_bounds__(512) detect_plain_kernel(fg_job J) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     detect_region(J, xcd_item(blockIdx.x, gridDim.x), smem);
+}
+
+// Levels MAX_FUSED.. of one frame, one region per block.
+__global__ void __launch_bounds__(512) detect_upper_plain_kernel(fg_job J) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    detect_region_upper(J, xcd_item(blockIdx.x, gridDim.x), smem);
+}
+
+// Levels MAX_FUSED.. of the batch's deep jobs, one listed region per block.
+__global__ void __launch_bounds__(512) detect_upper_batch_kernel(const fg_job *__restrict__ jobs,
+                                                                 const fg_item *__restrict__ items) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const fg_item it = items[blockIdx.x];
+    detect_region_upper(jobs[it.job], (int)it.region, smem);
 }
 
 // Persistent batched detector.  Work items are regions of all jobs
@@ -866,7 +919,7 @@ __global__ void __launch_bounds__(512) detect_batch_kernel(const fg_job *__restr
             Geo g0, g1, g2;
             build_fused(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1, st, smem, g0, g1, g2);
             if (threadIdx.x == 0 && next < total) ticket = atomicAdd(&counter[0], 1u);
-            run_passes(smem, g0, g1, g2, J.levels, R.P);
+            run_passes(smem, g0, g1, g2, fused_levels(J), R.P);
             if (threadIdx.x == 0) {
                 const unsigned cand = 2u * (unsigned)G + ticket;
                 s_next[b] = next < total && cand < (unsigned)total ? (int)cand : total;
@@ -930,7 +983,7 @@ __global__ void pyr_kernel(const uint8_t *__restrict__ src, int sp, uint8_t *__r
 
 __global__ void pyr_batch_kernel(const fg_job *__restrict__ jobs, int k) {
     const fg_job &J = jobs[blockIdx.z];
-    if (k >= J.levels || J.levels <= MAX_FUSED) return;
+    if (k >= J.levels || k < MAX_FUSED) return;
     const int w = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (4 * w >= J.w[k] || y >= J.h[k]) return;
     pyr_row_words(J.lvl[k - 1], J.pitch[k - 1], J.lvl[k], J.pitch[k], J.w[k], y, w);
@@ -967,31 +1020,44 @@ hipError_t fg_launch_pyramid(const fg_job &j, hipStream_t s) {
 }
 
 hipError_t fg_launch_plain(const fg_job &j, const fg_launch &L, hipStream_t s) {
-    if (j.levels > MAX_FUSED) {
-        hipError_t e = fg_launch_pyramid(j, s);
+    hipLaunchKernelGGL(detect_plain_kernel, dim3(j.rx * j.ry), dim3(L.block),
+                       fg_smem_bytes(L.block), s, j);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || j.levels <= MAX_FUSED) return e;
+    // deeper levels: built from the fused pass's last level, then detected
+    for (int k = MAX_FUSED; k < j.levels; ++k) {
+        dim3 grid(((j.w[k] + 3) / 4 + 63) / 64, j.h[k]);
+        hipLaunchKernelGGL(pyr_kernel, grid, dim3(64), 0, s, j.lvl[k - 1], j.pitch[k - 1], j.lvl[k],
+                           j.w[k], j.h[k], j.pitch[k]);
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(detect_plain_kernel, dim3(j.rx * j.ry), dim3(L.block),
+    hipLaunchKernelGGL(detect_upper_plain_kernel, dim3(j.rx * j.ry), dim3(L.block),
                        fg_smem_bytes(L.block), s, j);
     return hipGetLastError();
 }
 
 hipError_t fg_launch_batch(const fg_job *jobs_dev, const fg_item *items, int njobs, int total,
-                           int max_levels, int max_w1, int max_h1, unsigned *counter,
+                           int total_upper, int max_levels, int max_w1, int max_h1, unsigned *counter,
                            const fg_launch &L, hipStream_t s) {
-    int mw = max_w1, mh = max_h1;
-    for (int k = 1; k < max_levels && max_levels > MAX_FUSED; ++k) {
-        dim3 grid(((mw + 3) / 4 + 63) / 64, mh, njobs);
-        hipLaunchKernelGGL(pyr_batch_kernel, grid, dim3(64), 0, s, jobs_dev, k);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        mw = (mw >> 1) > 0 ? (mw >> 1) : 1;
-        mh = (mh >> 1) > 0 ? (mh >> 1) : 1;
-    }
     int blocks = L.num_cu * L.blocks_per_cu;
     if (blocks > total) blocks = total;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(detect_batch_kernel, dim3(blocks), dim3(L.block), fg_smem_bytes(L.block), s,
                        jobs_dev, items, total, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || total_upper == 0) return e;
+    int mw = max_w1, mh = max_h1;
+    for (int k = 2; k < max_levels; ++k) {
+        mw = (mw >> 1) > 0 ? (mw >> 1) : 1;
+        mh = (mh >> 1) > 0 ? (mh >> 1) : 1;
+        if (k < MAX_FUSED) continue;
+        dim3 grid(((mw + 3) / 4 + 63) / 64, mh, njobs);
+        hipLaunchKernelGGL(pyr_batch_kernel, grid, dim3(64), 0, s, jobs_dev, k);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(detect_upper_batch_kernel, dim3(total_upper), dim3(L.block), fg_smem_bytes(L.block),
+                       s, jobs_dev, items + total);
     return hipGetLastError();
 }

@@ -40,7 +40,7 @@ struct Plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int njobs = 0;
-    int total = 0, max_levels = 0, mw1 = 0, mh1 = 0;
+    int total = 0, total_upper = 0, max_levels = 0, mw1 = 0, mh1 = 0;
 };
 
 }  // namespace
@@ -163,11 +163,12 @@ int ticket_state(fast_ctx *c, uint64_t tk) {
     return hip_fail(c, e, "hipEventQuery");
 }
 
-int build_table(fast_ctx *c, const fast_job *jobs, int njobs, fg_job *table, int &total, int &max_levels,
-                int &max_w1, int &max_h1) {
+int build_table(fast_ctx *c, const fast_job *jobs, int njobs, fg_job *table, int &total, int &total_upper,
+                int &max_levels, int &max_w1, int &max_h1) {
     if (!jobs) return fail(c, FAST_EINVAL, "jobs is NULL");
     if (njobs < 1 || njobs > FAST_MAX_JOBS) return fail(c, FAST_EINVAL, "njobs not in 1..4096");
     total = 0;
+    total_upper = 0;
     max_levels = 1;
     max_w1 = 1;
     max_h1 = 1;
@@ -180,6 +181,7 @@ int build_table(fast_ctx *c, const fast_job *jobs, int njobs, fg_job *table, int
         }
         table[i].region_base = total;
         total += table[i].rx * table[i].ry;
+        if (q.levels > FG_MAX_FUSED) total_upper += table[i].rx * table[i].ry;
         if (q.levels > max_levels) max_levels = q.levels;
         if (q.levels > 1) {
             if (table[i].w[1] > max_w1) max_w1 = table[i].w[1];
@@ -193,6 +195,8 @@ int build_table(fast_ctx *c, const fast_job *jobs, int njobs, fg_job *table, int
 // regions clipped at a frame's right or bottom edge last, each group in job
 // and region order: the cheap items end the queue, so the persistent
 // workgroups run out of work closer together.
+// The regions of the jobs with more than FG_MAX_FUSED levels follow, in job
+// and region order, for the pass over their deeper levels.
 void fill_items(const fg_job *table, int njobs, fg_item *items) {
     int n = 0;
     for (int pass = 0; pass < 2; ++pass) {
@@ -206,6 +210,9 @@ void fill_items(const fg_job *table, int njobs, fg_item *items) {
             }
         }
     }
+    for (int j = 0; j < njobs; ++j)
+        if (table[j].levels > FG_MAX_FUSED)
+            for (int r = 0; r < table[j].rx * table[j].ry; ++r) items[n++] = fg_item{(uint32_t)j, (uint32_t)r};
 }
 
 }  // namespace
@@ -369,17 +376,18 @@ FG_API int fast_submit(fast_ctx *c, const fast_job *jobs, int njobs, void *strea
         e = hipMemset(S.counter, 0, FG_COUNTER_WORDS * sizeof(unsigned));
         if (e != hipSuccess) return hip_fail(c, e, "hipMemset counter");
     }
-    int total, max_levels, mw1, mh1;
-    int rc = build_table(c, jobs, njobs, S.host, total, max_levels, mw1, mh1);
+    int total, total_upper, max_levels, mw1, mh1;
+    int rc = build_table(c, jobs, njobs, S.host, total, total_upper, max_levels, mw1, mh1);
     if (rc) return rc;
-    if (total > S.items_cap) {
+    const int nitems = total + total_upper;
+    if (nitems > S.items_cap) {
         // the slot is idle, so its old map is no longer read by the device
         if (S.items_host) (void)hipHostFree(S.items_host);
         if (S.items_dev) (void)hipFree(S.items_dev);
         S.items_host = nullptr;
         S.items_dev = nullptr;
         S.items_cap = 0;
-        const int cap = total > 65536 ? total : 65536;
+        const int cap = nitems > 65536 ? nitems : 65536;
         hipError_t e = hipHostMalloc((void **)&S.items_host, sizeof(fg_item) * cap, hipHostMallocDefault);
         if (e != hipSuccess) { S.items_host = nullptr; return hip_fail(c, e, "hipHostMalloc item map"); }
         e = hipMalloc((void **)&S.items_dev, sizeof(fg_item) * cap);
@@ -390,9 +398,10 @@ FG_API int fast_submit(fast_ctx *c, const fast_job *jobs, int njobs, void *strea
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(S.dev, S.host, sizeof(fg_job) * njobs, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(c, e, "job table upload");
-    e = hipMemcpyAsync(S.items_dev, S.items_host, sizeof(fg_item) * total, hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(S.items_dev, S.items_host, sizeof(fg_item) * nitems, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(c, e, "item map upload");
-    e = fg_launch_batch(S.dev, S.items_dev, njobs, total, max_levels, mw1, mh1, S.counter, c->launch, s);
+    e = fg_launch_batch(S.dev, S.items_dev, njobs, total, total_upper, max_levels, mw1, mh1, S.counter,
+                        c->launch, s);
     if (e != hipSuccess) return hip_fail(c, e, "batch launch");
     rc = record_ticket(c, s, ticket);
     if (rc) return rc;
@@ -427,21 +436,22 @@ FG_API int fast_plan_create(fast_ctx *c, const fast_job *jobs, int njobs, int fl
     if (!plan_id) return fail(c, FAST_EINVAL, "plan_id is NULL");
     if (flags & ~FAST_PLAN_GRAPH) return fail(c, FAST_EINVAL, "unknown plan flags");
     std::vector<fg_job> table((size_t)(njobs > 0 ? njobs : 1));
-    int total, max_levels, mw1, mh1;
-    int rc = build_table(c, jobs, njobs, table.data(), total, max_levels, mw1, mh1);
+    int total, total_upper, max_levels, mw1, mh1;
+    int rc = build_table(c, jobs, njobs, table.data(), total, total_upper, max_levels, mw1, mh1);
     if (rc) return rc;
     DeviceGuard g(c->device);
     Plan p;
     p.njobs = njobs;
     p.total = total;
+    p.total_upper = total_upper;
     p.max_levels = max_levels;
     p.mw1 = mw1;
     p.mh1 = mh1;
-    std::vector<fg_item> items((size_t)total);
+    std::vector<fg_item> items((size_t)(total + total_upper));
     fill_items(table.data(), njobs, items.data());
     hipError_t e = hipMalloc((void **)&p.dev, sizeof(fg_job) * njobs);
     if (e != hipSuccess) return hip_fail(c, e, "hipMalloc plan table");
-    e = hipMalloc((void **)&p.items, sizeof(fg_item) * total);
+    e = hipMalloc((void **)&p.items, sizeof(fg_item) * (total + total_upper));
     if (e != hipSuccess) { (void)hipFree(p.dev); return hip_fail(c, e, "hipMalloc plan item map"); }
     e = hipMalloc((void **)&p.counter, FG_COUNTER_WORDS * sizeof(unsigned));
     if (e != hipSuccess) {
@@ -450,13 +460,14 @@ FG_API int fast_plan_create(fast_ctx *c, const fast_job *jobs, int njobs, int fl
         return hip_fail(c, e, "hipMalloc plan counter");
     }
     e = hipMemcpy(p.dev, table.data(), sizeof(fg_job) * njobs, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(p.items, items.data(), sizeof(fg_item) * total, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p.items, items.data(), sizeof(fg_item) * (total + total_upper), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p.counter, 0, FG_COUNTER_WORDS * sizeof(unsigned));
     if (e == hipSuccess && (flags & FAST_PLAN_GRAPH)) {
         if (!c->capture_stream) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t le = fg_launch_batch(p.dev, p.items, njobs, total, max_levels, mw1, mh1, p.counter,
+            hipError_t le = fg_launch_batch(p.dev, p.items, njobs, total, total_upper, max_levels, mw1, mh1, p.counter,
                                             c->launch, c->capture_stream);
             e = hipStreamEndCapture(c->capture_stream, &p.graph);
             if (le != hipSuccess) e = le;
@@ -484,7 +495,7 @@ FG_API int fast_plan_launch(fast_ctx *c, int plan_id, void *stream, uint64_t *ti
     hipStream_t s = (hipStream_t)stream;
     const Plan &p = c->plans[plan_id];
     hipError_t e = p.exec ? hipGraphLaunch(p.exec, s)
-                          : fg_launch_batch(p.dev, p.items, p.njobs, p.total, p.max_levels, p.mw1, p.mh1,
+                          : fg_launch_batch(p.dev, p.items, p.njobs, p.total, p.total_upper, p.max_levels, p.mw1, p.mh1,
                                             p.counter, c->launch, s);
     if (e != hipSuccess) return hip_fail(c, e, p.exec ? "hipGraphLaunch" : "plan launch");
     if (!ticket) return FAST_OK;

@@ -51,11 +51,16 @@ struct fg_item {
     uint32_t region;
 };
 
+// Pyramid levels detected from one level-0 load; deeper levels take a second
+// pass.
+constexpr int FG_MAX_FUSED = 3;
+
 // Batched path: `jobs_dev` is a device copy of njobs jobs whose region_base
-// fields are prefix sums; `total` is the number of work items and `items`
-// lists them (every region of every job once, in any order); `counter` holds
-// FG_COUNTER_WORDS zero-initialised words that the kernel re-arms itself on
-// exit.
+// fields are prefix sums.  items[0 .. total) lists every region of every job
+// once, in any order; items[total .. total + total_upper) lists every region
+// of the jobs with more than FG_MAX_FUSED levels (their deeper levels).
+// `counter` holds FG_COUNTER_WORDS zero-initialised words that the kernel
+// re-arms itself on exit.
 hipError_t fg_launch_batch(const fg_job *jobs_dev, const fg_item *items, int njobs, int total,
-                           int max_levels, int max_w1, int max_h1, unsigned *counter,
+                           int total_upper, int max_levels, int max_w1, int max_h1, unsigned *counter,
                            const fg_launch &L, hipStream_t s);
