@@ -255,14 +255,61 @@ __device__ __forceinline__ Seg make_seg(const Geo &g, bool on) {
     return q;
 }
 
+// Compass test of group i of the sub-tile's group sequence (i < total): the
+// 8-bit survivor mask, the LDS offset of the group's first pixel and its level.
+template <int K>
+__device__ __forceinline__ uint32_t compass_group(const uint8_t *smem, const Seg &s0, const Seg &s1,
+                                                  const Seg &s2, int b1, int b2, float inv0, float inv1,
+                                                  float inv2, s16x2 T1, int i, uint32_t &off,
+                                                  uint32_t &lvl) {
+    lvl = i < b1 ? 0u : (i < b2 ? 1u : 2u);
+    const int local = i - (lvl == 0 ? 0 : (lvl == 1 ? b1 : b2));
+    const int ppr = sel3(lvl, s0.ppr, s1.ppr, s2.ppr);
+    const float inv = lvl == 0 ? inv0 : (lvl == 1 ? inv1 : inv2);
+    const int row = (int)(((float)local + 0.5f) * inv), pp = local - row * ppr;
+    off = (uint32_t)(sel3(lvl, s0.tbase, s1.tbase, s2.tbase) +
+                     (sel3(lvl, s0.r0, s1.r0, s2.r0) + row) * LP + sel3(lvl, s0.gc0, s1.gc0, s2.gc0) + 8 * pp);
+    if constexpr (K > 0) {
+        const uint8_t *p = smem + off;
+        const uint32_t D0 = *(const uint32_t *)(p - 4);
+        const uint32_t D1 = *(const uint32_t *)(p);
+        const uint32_t D2 = *(const uint32_t *)(p + 4);
+        const uint32_t D3 = *(const uint32_t *)(p + 8);
+        const uint32_t N0 = *(const uint32_t *)(p - 3 * LP);
+        const uint32_t N1 = *(const uint32_t *)(p - 3 * LP + 4);
+        const uint32_t S0 = *(const uint32_t *)(p + 3 * LP);
+        const uint32_t S1 = *(const uint32_t *)(p + 3 * LP + 4);
+        const uint32_t r01 = as_u32(compass<K>(
+            pair(D1, D1, 0x0c010c00u), pair(N0, N0, 0x0c010c00u), pair(D2, D1, 0x0c040c03u),
+            pair(S0, S0, 0x0c010c00u), pair(D1, D0, 0x0c020c01u), T1));
+        const uint32_t r23 = as_u32(compass<K>(
+            pair(D1, D1, 0x0c030c02u), pair(N0, N0, 0x0c030c02u), pair(D2, D1, 0x0c060c05u),
+            pair(S0, S0, 0x0c030c02u), pair(D1, D0, 0x0c040c03u), T1));
+        const uint32_t r45 = as_u32(compass<K>(
+            pair(D2, D2, 0x0c010c00u), pair(N1, N1, 0x0c010c00u), pair(D3, D2, 0x0c040c03u),
+            pair(S1, S1, 0x0c010c00u), pair(D2, D1, 0x0c020c01u), T1));
+        const uint32_t r67 = as_u32(compass<K>(
+            pair(D2, D2, 0x0c030c02u), pair(N1, N1, 0x0c030c02u), pair(D3, D2, 0x0c060c05u),
+            pair(S1, S1, 0x0c030c02u), pair(D2, D1, 0x0c040c03u), T1));
+        // sign bit of each 16-bit lane = rejected; bit j <- pixel 2j,
+        // bit 4+j <- pixel 2j+1
+        const uint32_t sg = ((r01 >> 15) & 0x10001u) | ((r23 >> 14) & 0x20002u) |
+                            ((r45 >> 13) & 0x40004u) | ((r67 >> 12) & 0x80008u);
+        return ~(sg | (sg >> 12)) & 0xFFu;
+    } else {
+        return 0xFFu;
+    }
+}
+
 // P1+P2: compass test of every scored pixel of every level, 8 pixels per
 // lane in packed 16-bit lanes.  The groups of all levels form one sequence
 // dealt to the waves round-robin in rounds of 64, so every wave does the
-// same share whatever the level sizes.  Groups with a survivor are compacted
-// into the wave's group list (ballot + mbcnt; word = level << 22 | LDS
-// offset of the group << 8 | survivor mask), which is then expanded into the
-// wave's pixel list, keeping testable pixels only; an entry is
-// (level << 14) | LDS offset of the pixel.  Returns the wave's pixel count.
+// same share whatever the level sizes; a wave tests two rounds at a time so
+// that the LDS reads of one overlap the arithmetic of the other.  Groups with
+// a survivor are compacted into the wave's group list (ballot + mbcnt; word =
+// level << 22 | LDS offset of the group << 8 | survivor mask), which is then
+// expanded into the wave's pixel list, keeping testable pixels only; an entry
+// is (level << 14) | LDS offset of the pixel.  Returns the wave's pixel count.
 template <int K>
 __device__ int collect(const uint8_t *smem, const Seg &s0, const Seg &s1, const Seg &s2, int t,
                        uint32_t *blist, uint16_t *list) {
@@ -275,55 +322,27 @@ __device__ int collect(const uint8_t *smem, const Seg &s0, const Seg &s1, const 
                 inv1 = __builtin_amdgcn_rcpf((float)max(s1.ppr, 1)),
                 inv2 = __builtin_amdgcn_rcpf((float)max(s2.ppr, 1));
     const s16x2 T1 = {(short)(t + 1), (short)(t + 1)};
+    const int stride = nwaves * 64;
     int nb = 0;
-    for (int i0 = wave * 64; i0 < total; i0 += nwaves * 64) {
-        const int i = i0 + lane;
-        uint32_t sv = 0, off = 0, lvl = 0;
-        if (i < total) {
-            lvl = i < b1 ? 0u : (i < b2 ? 1u : 2u);
-            const int local = i - (lvl == 0 ? 0 : (lvl == 1 ? b1 : b2));
-            const int ppr = sel3(lvl, s0.ppr, s1.ppr, s2.ppr);
-            const float inv = lvl == 0 ? inv0 : (lvl == 1 ? inv1 : inv2);
-            const int row = (int)(((float)local + 0.5f) * inv), pp = local - row * ppr;
-            off = (uint32_t)(sel3(lvl, s0.tbase, s1.tbase, s2.tbase) +
-                             (sel3(lvl, s0.r0, s1.r0, s2.r0) + row) * LP + sel3(lvl, s0.gc0, s1.gc0, s2.gc0) +
-                             8 * pp);
-            if constexpr (K > 0) {
-                const uint8_t *p = smem + off;
-                const uint32_t D0 = *(const uint32_t *)(p - 4);
-                const uint32_t D1 = *(const uint32_t *)(p);
-                const uint32_t D2 = *(const uint32_t *)(p + 4);
-                const uint32_t D3 = *(const uint32_t *)(p + 8);
-                const uint32_t N0 = *(const uint32_t *)(p - 3 * LP);
-                const uint32_t N1 = *(const uint32_t *)(p - 3 * LP + 4);
-                const uint32_t S0 = *(const uint32_t *)(p + 3 * LP);
-                const uint32_t S1 = *(const uint32_t *)(p + 3 * LP + 4);
-                const uint32_t r01 = as_u32(compass<K>(
-                    pair(D1, D1, 0x0c010c00u), pair(N0, N0, 0x0c010c00u), pair(D2, D1, 0x0c040c03u),
-                    pair(S0, S0, 0x0c010c00u), pair(D1, D0, 0x0c020c01u), T1));
-                const uint32_t r23 = as_u32(compass<K>(
-                    pair(D1, D1, 0x0c030c02u), pair(N0, N0, 0x0c030c02u), pair(D2, D1, 0x0c060c05u),
-                    pair(S0, S0, 0x0c030c02u), pair(D1, D0, 0x0c040c03u), T1));
-                const uint32_t r45 = as_u32(compass<K>(
-                    pair(D2, D2, 0x0c010c00u), pair(N1, N1, 0x0c010c00u), pair(D3, D2, 0x0c040c03u),
-                    pair(S1, S1, 0x0c010c00u), pair(D2, D1, 0x0c020c01u), T1));
-                const uint32_t r67 = as_u32(compass<K>(
-                    pair(D2, D2, 0x0c030c02u), pair(N1, N1, 0x0c030c02u), pair(D3, D2, 0x0c060c05u),
-                    pair(S1, S1, 0x0c030c02u), pair(D2, D1, 0x0c040c03u), T1));
-                // sign bit of each 16-bit lane = rejected; bit j <- pixel 2j,
-                // bit 4+j <- pixel 2j+1
-                const uint32_t sg = ((r01 >> 15) & 0x10001u) | ((r23 >> 14) & 0x20002u) |
-                                    ((r45 >> 13) & 0x40004u) | ((r67 >> 12) & 0x80008u);
-                sv = ~(sg | (sg >> 12)) & 0xFFu;
-            } else {
-                sv = 0xFFu;
-            }
-        }
-        const uint64_t bal = __ballot(sv != 0);
-        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        if (sv) blist[nb + rank] = (lvl << 22) | (off << 8) | sv;
-        nb += __popcll(bal);
+    for (int i0 = wave * 64; i0 < total; i0 += 2 * stride) {
+        const int ia = i0 + lane, ib = i0 + stride + lane;
+        uint32_t offa = 0, lvla = 0, offb = 0, lvlb = 0;
+        const uint32_t sva = ia < total ? compass_group<K>(smem, s0, s1, s2, b1, b2, inv0, inv1, inv2, T1, ia,
+                                                           offa, lvla)
+                                        : 0u;
+        const uint32_t svb = ib < total ? compass_group<K>(smem, s0, s1, s2, b1, b2, inv0, inv1, inv2, T1, ib,
+                                                           offb, lvlb)
+                                        : 0u;
+        const uint64_t bala = __ballot(sva != 0);
+        const int ranka = __builtin_amdgcn_mbcnt_hi((uint32_t)(bala >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bala, 0u));
+        if (sva) blist[nb + ranka] = (lvla << 22) | (offa << 8) | sva;
+        nb += __popcll(bala);
+        const uint64_t balb = __ballot(svb != 0);
+        const int rankb = __builtin_amdgcn_mbcnt_hi((uint32_t)(balb >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)balb, 0u));
+        if (svb) blist[nb + rankb] = (lvlb << 22) | (offb << 8) | svb;
+        nb += __popcll(balb);
     }
     wave_sync();
     int count = 0;
@@ -877,7 +896,9 @@ __global__ void __launch_bounds__(512) detect_upper_batch_kernel(const fg_job *_
 //   * when a region is a single fused sub-tile (and the workgroup has >= 256
 //     threads), the level-0 tile of the next region is loaded into registers
 //     during the passes of the current one.
-__global__ void __launch_bounds__(512) detect_batch_kernel(const fg_job *__restrict__ jobs,
+// Three workgroups of 256 threads share a CU (LDS-bound), so the register
+// budget is capped at three waves per SIMD.
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))) detect_batch_kernel(const fg_job *__restrict__ jobs,
                                                            const fg_item *__restrict__ items,
                                                            int total, unsigned *counter) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
