@@ -58,6 +58,10 @@ def load() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} missing: build it with __graft_entry__.build()")
+        # torch ships its own HIP runtime under the same soname; loading torch
+        # first makes the library bind to that one, so the process holds a
+        # single HIP runtime and torch's streams and memory are valid here.
+        import torch  # noqa: F401
         lib = ctypes.CDLL(LIB_PATH)
         vp, i32, u64p = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)
         P = ctypes.POINTER(fast_plane)

@@ -22,9 +22,9 @@ from . import fastgrid
 
 DEFAULT_SHAPE = (64, 256, 3)
 CANDIDATES = [
-    (64, 256, 2), (64, 256, 3), (64, 256, 4), (64, 256, 8),
-    (64, 512, 1), (64, 512, 2), (64, 512, 4),
-    (64, 128, 4), (64, 128, 8), (128, 256, 3), (128, 512, 2), (32, 256, 4),
+    (64, 256, 2), (64, 256, 3), (64, 256, 4),
+    (64, 512, 1), (64, 512, 2),
+    (64, 128, 4), (64, 128, 6), (128, 256, 3), (128, 512, 2), (32, 256, 3), (32, 256, 4),
 ]
 
 
@@ -129,3 +129,27 @@ def load_best(path: str, specs):
         cache = json.load(f)
     hit = cache.get(signature(specs))
     return tuple(hit["best"]) if hit else None
+
+
+def main(argv=None) -> int:
+    """Tune the launch shape on the 64-frame batch workload and print the table;
+    with --out, merge the result into a JSON cache."""
+    import argparse
+    from . import synth
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--reps", type=int, default=30)
+    ap.add_argument("--out", default="")
+    args = ap.parse_args(argv)
+    ctx = fastgrid.Context(0)
+    specs = synth.batch64()
+    frames = [s.make() for s in specs]
+    res = tune(ctx, specs, frames, reps=args.reps, log=lambda m: print(m, flush=True))
+    print(json.dumps({"best": res["best"], "table": res["table"]}))
+    if args.out:
+        save(res, args.out)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

@@ -180,3 +180,34 @@ def test_submit_rejects_bad_job_and_enqueues_nothing(ctx, batch):
 def test_poll_unknown_ticket(ctx):
     with pytest.raises(fastgrid.FastError):
         ctx.poll(10 ** 12)
+
+
+@pytest.mark.parametrize("shape", [(64, 256, 3), (128, 256, 3), (256, 512, 2), (32, 128, 4)],
+                         ids=["r64", "r128", "r256", "r32_b128"])
+def test_batch_launch_shapes_with_deep_levels(ctx, shape):
+    """The persistent kernel with regions of several sub-tiles (no register
+    prefetch), small workgroups, and jobs of 1..5 levels, so the fused pass
+    and the deep-level pass both run inside one submission."""
+    rng = np.random.default_rng(77)
+    specs, frames, want = [], [], []
+    for i in range(12):
+        levels = 1 + i % 5
+        w = int(rng.integers(max(64, 7 << (levels - 1)), 700))
+        h = int(rng.integers(max(48, 7 << (levels - 1)), 500))
+        cell = int(rng.choice([16, 32, 64]))
+        s = synth.FrameSpec(w, h, levels, synth.BATCH_T[i % 4], synth.BATCH_N[i % 3], cell,
+                            seed=900 + i, nshapes=80, sigma=4.0)
+        img = s.make()
+        specs.append(s)
+        frames.append(img)
+        slots, planes = oracle.detect_grid(img, w, levels, s.t, s.n, cell)
+        want.append((slots, [p[:, :pw].copy() for p, pw in planes]))
+    print(f"case batch shape {shape}", flush=True)
+    try:
+        ctx.set_launch(*shape)
+        pyrs, grids, jobs = make_resident(specs, frames)
+        tk = ctx.submit(jobs)
+        assert ctx.wait(tk, 60_000)
+        check_all(specs, pyrs, grids, want, f"shape {shape}")
+    finally:
+        ctx.set_launch(64, 256, 3)

@@ -154,3 +154,29 @@ def test_invalid_arguments_enqueue_nothing(ctx):
         fastgrid.fast_detect_grid(ctx.handle, planes, 2, 10, 9, 16, grid.ptr)
     with pytest.raises(fastgrid.FastError):
         fastgrid.fast_detect_grid(ctx.handle, pyr.planes, 2, 10, 9, 16, 0)
+
+
+def test_largest_stream_frame_4096x2160_five_levels(ctx):
+    """The largest frame of the camera-stream workload (4096x2160, 5 levels)
+    through the plain path and through a one-job batch, every slot and level
+    against the oracle."""
+    spec = synth.streams32()[3]
+    assert (spec.width, spec.height) == (4096, 2160)
+    img = spec.frame(0)
+    print("case 4096x2160 L=5", flush=True)
+    got, lv = run_plain(ctx, img, spec.width, 5, spec.t, spec.n, spec.cell)
+    check_against_oracle(got, lv, img, spec.width, 5, spec.t, spec.n, spec.cell, "4k plain")
+    pyr = fastgrid.Pyramid(spec.width, spec.height, 5)
+    pyr.upload(img)
+    grid = fastgrid.Grid(spec.width, spec.height, spec.cell)
+    jobs = fastgrid.Context.make_jobs([(pyr, spec.t, spec.n, spec.cell, grid)])
+    assert ctx.wait(ctx.submit(jobs), 60_000)
+    assert np.array_equal(grid.fetch(), got)
+
+
+@pytest.mark.parametrize("w,h,levels,cell", [(8192, 16, 1, 16), (16, 4096, 2, 16), (6000, 40, 3, 32)])
+def test_extreme_aspect_ratios(ctx, w, h, levels, cell):
+    print(f"case aspect {w}x{h} L={levels}", flush=True)
+    img = synth.frame(w, h, seed=w + h, nshapes=30, sigma=5, pad_garbage=True)
+    got, lv = run_plain(ctx, img, w, levels, 10, 9, cell)
+    check_against_oracle(got, lv, img, w, levels, 10, 9, cell, f"aspect {w}x{h}")
