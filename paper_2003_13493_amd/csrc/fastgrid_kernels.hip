@@ -36,7 +36,7 @@
 
 namespace {
 
-constexpr int SUB = 64;                 // sub-tile side at level 0
+constexpr int SUB = FG_SUB;             // sub-tile side at level 0
 constexpr int MAX_FUSED = FG_MAX_FUSED;   // levels built in LDS from one load
 
 // All level tiles share one LDS row pitch, so circle offsets are constants.
@@ -65,7 +65,8 @@ constexpr int OFF_M0 = TILE_BYTES;
 constexpr int OFF_M1 = OFF_M0 + M0_ROWS * M0_P * 2;
 constexpr int OFF_M2 = OFF_M1 + M1_ROWS * M1_P * 2;
 constexpr int OFF_KEYS = (OFF_M2 + M2_ROWS * M2_P * 2 + 15) & ~15;
-constexpr int OFF_WAVES = OFF_KEYS + MAX_KEYS * 4;
+constexpr int OFF_KEYS2 = OFF_KEYS + MAX_KEYS * 4;   // second buffer for the pipelined kernel
+constexpr int OFF_WAVES = OFF_KEYS2 + MAX_KEYS * 4;
 static_assert(OFF_WAVES % 16 == 0, "aligned scratch");
 
 // Per-wave scratch for V waves.  Compass rounds are dealt to the waves in
@@ -452,13 +453,21 @@ __device__ __forceinline__ LevelMap level_map(const Geo &g, int band_row, int ba
 // fold the survivors into the region's cell keys.  P1-P4 run on every wave
 // without workgroup barriers; one barrier makes all scores visible before
 // NMS.
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
+// `before` runs on every thread just before the barrier that separates
+// scoring from NMS, `after` just after it (the pipelined kernel uses them to
+// publish its next work item and to reuse the level-0 tile, which NMS no
+// longer reads).
+template <class Before = NoHook, class After = NoHook>
 __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Geo &g2, int nl,
-                           const Params &P) {
+                           const Params &P, uint32_t *keys, Before before = Before(), After after = After()) {
     const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     uint8_t *scratch = smem + OFF_WAVES + wave * wave_bytes(nwaves);
     uint32_t *blist = (uint32_t *)scratch;
     uint16_t *list = (uint16_t *)(scratch + blist_cap(nwaves) * 4);
-    uint32_t *keys = (uint32_t *)(smem + OFF_KEYS);
     const Seg s0 = make_seg(g0, has_area(g0));
     const Seg s1 = make_seg(g1, nl > 1 && has_area(g1));
     const Seg s2 = make_seg(g2, nl > 2 && has_area(g2));
@@ -489,7 +498,9 @@ __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Ge
                 (uint16_t)s;
         }
     }
+    before();
     __syncthreads();   // every level's scores, ring included, are in the maps
+    after();
     // P5: 3x3 NMS of the sub-tile's own pixels, then the cell keys
     for (int i = lane; i < n2; i += 64) {
         const uint16_t e = list[i];
@@ -671,8 +682,10 @@ __device__ __forceinline__ Stage fused_stage(const fg_job &J, int sx0, int sy0, 
 
 // With level 0 of a fused sub-tile in LDS: build levels 1.. in LDS, describe
 // every level, and write levels 1.. of the sub-tile to their planes.
+// sync_first: a barrier must separate the level-0 tile's commit from the
+// halving (the pipelined kernel has one already).
 __device__ void build_fused(const fg_job &J, int sx0, int sy0, int xr1, int yr1, const Stage &st,
-                            uint8_t *smem, Geo &g0, Geo &g1, Geo &g2) {
+                            uint8_t *smem, Geo &g0, Geo &g1, Geo &g2, bool sync_first = true) {
     level_area(J, 0, sx0, sy0, xr1, yr1, g0);
     g0.tbase = T0;
     g0.tx = st.tx;
@@ -684,7 +697,7 @@ __device__ void build_fused(const fg_job &J, int sx0, int sy0, int xr1, int yr1,
     g2 = g0;
     const int nl = fused_levels(J);
     if (nl > 1) {
-        __syncthreads();
+        if (sync_first) __syncthreads();
         halve_two(smem + T0, smem + T1, smem + T2, st.tw, st.th, nl > 2);
         level_area(J, 1, sx0, sy0, xr1, yr1, g1);
         g1.tbase = T1;
@@ -721,7 +734,7 @@ __device__ void process_subtile(const fg_job &J, int sx0, int sy0, int xr1, int 
     zero_lds(smem + OFF_M0, OFF_KEYS - OFF_M0);
     Geo g0, g1, g2;
     build_fused(J, sx0, sy0, xr1, yr1, st, smem, g0, g1, g2);
-    run_passes(smem, g0, g1, g2, fused_levels(J), P);
+    run_passes(smem, g0, g1, g2, fused_levels(J), P, (uint32_t *)(smem + OFF_KEYS));
 }
 
 // Levels MAX_FUSED .. L-1 of one level-0 sub-tile (already built in their
@@ -744,7 +757,7 @@ __device__ void process_subtile_upper(const fg_job &J, int sx0, int sy0, int xr1
         g.moff = OFF_M0;
         g.mp = M0_P;
         set_groups(g);
-        run_passes(smem, g, g, g, 1, P);
+        run_passes(smem, g, g, g, 1, P, (uint32_t *)(smem + OFF_KEYS));
     }
 }
 
@@ -844,10 +857,6 @@ __device__ void detect_region_upper(const fg_job &J, int region, uint8_t *smem) 
     keys_write(J, R, keys);
 }
 
-// A region is one fused sub-tile when it is at most one sub-tile wide and
-// tall.
-__device__ __forceinline__ bool single_fused(const fg_job &J) { return J.rcells * J.cell <= SUB; }
-
 // Issue the level-0 tile loads of a single-fused-sub-tile region.
 __device__ __forceinline__ void region_prefetch(const fg_job &J, int region, TileRegs &T) {
     const Region R = region_of(J, region);
@@ -883,90 +892,14 @@ __global__ void __launch_bounds__(512) detect_upper_batch_kernel(const fg_job *_
     detect_region_upper(jobs[it.job], (int)it.region, smem);
 }
 
-// Persistent batched detector.  Work items are regions of all jobs
-// (items[] gives each one's job and region).  Latencies are taken off the critical
-// path by working ahead:
-//   * the first two items of a workgroup are fixed, and the queue ticket of
-//     the item after next is drawn before the detection passes of the
-//     current region and resolved after them, so the atomic's round trip,
-//     and any wait for earlier stores, overlaps the passes;
-//   * the job of the item after next is looked up while the current region
-//     finishes, and the next item's job is read while waiting for the
-//     previous region's last wave;
-//   * when a region is a single fused sub-tile (and the workgroup has >= 256
-//     threads), the level-0 tile of the next region is loaded into registers
-//     during the passes of the current one.
-// Three workgroups of 256 threads share a CU (LDS-bound), so the register
-// budget is capped at three waves per SIMD.
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))) detect_batch_kernel(const fg_job *__restrict__ jobs,
-                                                           const fg_item *__restrict__ items,
-                                                           int total, unsigned *counter) {
-    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    // Work items: workgroup g starts with items g and g + G (G blocks, at most
-    // `total`); the rest are handed out by an atomic counter, ticket k being
-    // item 2G + k.  A workgroup always knows its current and its next item,
-    // and draws the ticket of the one after during the current detection.
-    // s_next[b] carries that item from thread 0 to the workgroup; the two
-    // buffers alternate, so a value is never overwritten before every wave
-    // has read it.
-    __shared__ int s_next[2];
-    uint32_t *keys = (uint32_t *)(smem + OFF_KEYS);
-    const bool pipe = blockDim.x >= 256;   // four tile rows per thread cover a fused tile
-    const int G = (int)gridDim.x;
-    int item = (int)blockIdx.x;
-    int next = item + G < total ? item + G : total;
-    fg_item il = items[item];
-    fg_item in = next < total ? items[next] : fg_item{0u, 0u};
-    int b = 0;
-    TileRegs T;
-    if (pipe) {
-        const fg_job &J = jobs[il.job];
-        if (single_fused(J)) region_prefetch(J, (int)il.region, T);
-    }
-    while (item < total) {
-        const fg_job &J = jobs[il.job];    // uniform: read through the scalar cache
-        const fg_job &Jn = jobs[in.job];   // the next item's job, read while waiting below
-        const int region = (int)il.region;
-        unsigned ticket = 0;
-        int after;
-        if (pipe && single_fused(J)) {
-            const Region R = region_of(J, region);
-            const Stage st = fused_stage(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1);
-            __syncthreads();   // the previous region is done with LDS
-            tile_commit(smem + T0, T, st.tw, st.th);
-            if (next < total && single_fused(Jn)) region_prefetch(Jn, (int)in.region, T);
-            zero_lds(smem + OFF_M0, OFF_KEYS - OFF_M0);
-            keys_clear(keys, R.ncx * R.ncy);
-            Geo g0, g1, g2;
-            build_fused(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1, st, smem, g0, g1, g2);
-            if (threadIdx.x == 0 && next < total) ticket = atomicAdd(&counter[0], 1u);
-            run_passes(smem, g0, g1, g2, fused_levels(J), R.P);
-            if (threadIdx.x == 0) {
-                const unsigned cand = 2u * (unsigned)G + ticket;
-                s_next[b] = next < total && cand < (unsigned)total ? (int)cand : total;
-            }
-            __syncthreads();   // publishes s_next[b]
-            after = s_next[b];
-            keys_write(J, R, keys);
-        } else {
-            if (threadIdx.x == 0 && next < total) ticket = atomicAdd(&counter[0], 1u);
-            detect_region(J, region, smem);
-            if (threadIdx.x == 0) {
-                const unsigned cand = 2u * (unsigned)G + ticket;
-                s_next[b] = next < total && cand < (unsigned)total ? (int)cand : total;
-            }
-            __syncthreads();
-            after = s_next[b];
-            if (next < total && pipe && single_fused(Jn)) region_prefetch(Jn, (int)in.region, T);
-        }
-        item = next;
-        next = after;
-        il = in;
-        in = after < total ? items[after] : fg_item{0u, 0u};
-        b ^= 1;
-    }
-    // Every drawn ticket has been resolved.  The last workgroup out re-arms
-    // the queues for the next launch.
+// Persistent batched detectors.  Work items are regions of all jobs (items[]
+// gives each one's job and region).  Workgroup g starts with items g and
+// g + G (G blocks, at most `total`); the rest are handed out by an atomic
+// counter, ticket k being item 2G + k, re-armed by the last workgroup out.
+
+// The last workgroup out re-arms the queue for the next launch (every ticket
+// a workgroup drew has been resolved by then).
+__device__ __forceinline__ void queue_exit(unsigned *counter) {
     if (threadIdx.x == 0) {
         __threadfence();
         const unsigned done = atomicAdd(&counter[1], 1u);
@@ -975,6 +908,124 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8))
             atomicExch(&counter[1], 0u);
         }
     }
+}
+
+// Pipelined kernel, for batches whose regions are all single fused sub-tiles
+// and workgroups of at least 256 threads (four tile rows per thread cover a
+// fused tile).  Per region there are three workgroup barriers:
+//   [A] the previous region's NMS is done and this region's level-0 tile is
+//       in LDS: write the previous region's slots, clear the score maps and
+//       this region's cell keys (two key buffers alternate), build levels
+//       1-2 in LDS;
+//   [B] write levels 1-2, draw the ticket of the region after next, run the
+//       compass, 8-point and scoring passes; thread 0 resolves the ticket;
+//   [C] the scores are complete and the tile is no longer read: commit the
+//       next region's tile (loaded into registers one region earlier) to
+//       LDS, start loading the tile after it, then run NMS into the keys.
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8)))
+detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__ items, int total,
+                    unsigned *counter) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    // s_next[b] carries the item after next from thread 0 to the workgroup;
+    // the two buffers alternate, so a value is never overwritten before every
+    // wave has read it.
+    __shared__ int s_next[2];
+    const int G = (int)gridDim.x;
+    int item = (int)blockIdx.x;
+    int next = item + G < total ? item + G : total;
+    fg_item il = items[item];
+    fg_item in = next < total ? items[next] : fg_item{0u, 0u};
+    TileRegs T;
+    {
+        const fg_job &J = jobs[il.job];
+        const Region R = region_of(J, (int)il.region);
+        const Stage st = fused_stage(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1);
+        region_prefetch(J, (int)il.region, T);
+        tile_commit(smem + T0, T, st.tw, st.th);
+        if (next < total) region_prefetch(jobs[in.job], (int)in.region, T);
+    }
+    fg_item prev{0u, 0u};
+    bool have_prev = false;
+    int b = 0;
+    while (item < total) {
+        const fg_job &J = jobs[il.job];   // uniform: read through the scalar cache
+        const Region R = region_of(J, (int)il.region);
+        const Stage st = fused_stage(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1);
+        uint32_t *keys = (uint32_t *)(smem + (b ? OFF_KEYS2 : OFF_KEYS));
+        __syncthreads();   // [A]
+        if (have_prev) {
+            const fg_job &Jp = jobs[prev.job];
+            keys_write(Jp, region_of(Jp, (int)prev.region), (const uint32_t *)(smem + (b ? OFF_KEYS : OFF_KEYS2)));
+        }
+        zero_lds(smem + OFF_M0, OFF_KEYS - OFF_M0);
+        keys_clear(keys, R.ncx * R.ncy);
+        Geo g0, g1, g2;
+        build_fused(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1, st, smem, g0, g1, g2, false);   // ends with [B]
+        unsigned ticket = 0;
+        if (threadIdx.x == 0 && next < total) ticket = atomicAdd(&counter[0], 1u);
+        int after = total;
+        run_passes(
+            smem, g0, g1, g2, fused_levels(J), R.P, keys,
+            [&]() {
+                if (threadIdx.x == 0) {
+                    const unsigned cand = 2u * (unsigned)G + ticket;
+                    s_next[b] = next < total && cand < (unsigned)total ? (int)cand : total;
+                }
+            },
+            [&]() {   // after [C]
+                after = __builtin_amdgcn_readfirstlane(s_next[b]);
+                if (next < total) {
+                    const fg_job &Jn = jobs[in.job];
+                    const Region Rn = region_of(Jn, (int)in.region);
+                    const Stage sn = fused_stage(Jn, Rn.P.rx0, Rn.P.ry0, Rn.xr1, Rn.yr1);
+                    tile_commit(smem + T0, T, sn.tw, sn.th);
+                    if (after < total) {
+                        const fg_item ia = items[after];
+                        region_prefetch(jobs[ia.job], (int)ia.region, T);
+                    }
+                }
+            });
+        prev = il;
+        have_prev = true;
+        item = next;
+        il = in;
+        next = after;
+        in = after < total ? items[after] : fg_item{0u, 0u};
+        b ^= 1;
+    }
+    __syncthreads();
+    if (have_prev) {   // the last region used the buffer before the final flip of b
+        const fg_job &Jp = jobs[prev.job];
+        keys_write(Jp, region_of(Jp, (int)prev.region), (const uint32_t *)(smem + (b ? OFF_KEYS : OFF_KEYS2)));
+    }
+    queue_exit(counter);
+}
+
+// Generic persistent kernel: any region size and workgroup size, one region
+// at a time.
+__global__ void __launch_bounds__(512) detect_batch_generic_kernel(const fg_job *__restrict__ jobs,
+                                                                   const fg_item *__restrict__ items,
+                                                                   int total, unsigned *counter) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    __shared__ int s_item;
+    const int G = (int)gridDim.x;
+    for (int k = 0;; ++k) {
+        __syncthreads();   // every wave has read the previous s_item
+        if (threadIdx.x == 0) {
+            int it = (int)blockIdx.x + k * G;
+            if (k >= 2) {
+                const unsigned t = atomicAdd(&counter[0], 1u);
+                it = 2 * G + (int)min(t, (unsigned)total);
+            }
+            s_item = it < total ? it : total;
+        }
+        __syncthreads();
+        const int item = s_item;
+        if (item >= total) break;
+        const fg_item it = items[item];
+        detect_region(jobs[it.job], (int)it.region, smem);
+    }
+    queue_exit(counter);
 }
 
 // Pyramid level k from level k-1, four output pixels per thread.
@@ -1059,13 +1110,17 @@ hipError_t fg_launch_plain(const fg_job &j, const fg_launch &L, hipStream_t s) {
 }
 
 hipError_t fg_launch_batch(const fg_job *jobs_dev, const fg_item *items, int njobs, int total,
-                           int total_upper, int max_levels, int max_w1, int max_h1, unsigned *counter,
-                           const fg_launch &L, hipStream_t s) {
+                           int total_upper, int max_levels, int max_w1, int max_h1, bool all_single,
+                           unsigned *counter, const fg_launch &L, hipStream_t s) {
     int blocks = L.num_cu * L.blocks_per_cu;
     if (blocks > total) blocks = total;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(detect_batch_kernel, dim3(blocks), dim3(L.block), fg_smem_bytes(L.block), s,
-                       jobs_dev, items, total, counter);
+    if (all_single && L.block >= 256)
+        hipLaunchKernelGGL(detect_batch_kernel, dim3(blocks), dim3(L.block), fg_smem_bytes(L.block), s,
+                           jobs_dev, items, total, counter);
+    else
+        hipLaunchKernelGGL(detect_batch_generic_kernel, dim3(blocks), dim3(L.block), fg_smem_bytes(L.block), s,
+                           jobs_dev, items, total, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || total_upper == 0) return e;
     int mw = max_w1, mh = max_h1;

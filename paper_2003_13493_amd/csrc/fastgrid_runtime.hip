@@ -41,6 +41,7 @@ struct Plan {
     hipGraphExec_t exec = nullptr;
     int njobs = 0;
     int total = 0, total_upper = 0, max_levels = 0, mw1 = 0, mh1 = 0;
+    bool all_single = true;
 };
 
 }  // namespace
@@ -164,11 +165,12 @@ int ticket_state(fast_ctx *c, uint64_t tk) {
 }
 
 int build_table(fast_ctx *c, const fast_job *jobs, int njobs, fg_job *table, int &total, int &total_upper,
-                int &max_levels, int &max_w1, int &max_h1) {
+                int &max_levels, int &max_w1, int &max_h1, bool &all_single) {
     if (!jobs) return fail(c, FAST_EINVAL, "jobs is NULL");
     if (njobs < 1 || njobs > FAST_MAX_JOBS) return fail(c, FAST_EINVAL, "njobs not in 1..4096");
     total = 0;
     total_upper = 0;
+    all_single = true;
     max_levels = 1;
     max_w1 = 1;
     max_h1 = 1;
@@ -182,6 +184,7 @@ int build_table(fast_ctx *c, const fast_job *jobs, int njobs, fg_job *table, int
         table[i].region_base = total;
         total += table[i].rx * table[i].ry;
         if (q.levels > FG_MAX_FUSED) total_upper += table[i].rx * table[i].ry;
+        if (table[i].rcells * table[i].cell > FG_SUB) all_single = false;
         if (q.levels > max_levels) max_levels = q.levels;
         if (q.levels > 1) {
             if (table[i].w[1] > max_w1) max_w1 = table[i].w[1];
@@ -377,7 +380,8 @@ FG_API int fast_submit(fast_ctx *c, const fast_job *jobs, int njobs, void *strea
         if (e != hipSuccess) return hip_fail(c, e, "hipMemset counter");
     }
     int total, total_upper, max_levels, mw1, mh1;
-    int rc = build_table(c, jobs, njobs, S.host, total, total_upper, max_levels, mw1, mh1);
+    bool all_single;
+    int rc = build_table(c, jobs, njobs, S.host, total, total_upper, max_levels, mw1, mh1, all_single);
     if (rc) return rc;
     const int nitems = total + total_upper;
     if (nitems > S.items_cap) {
@@ -400,8 +404,8 @@ FG_API int fast_submit(fast_ctx *c, const fast_job *jobs, int njobs, void *strea
     if (e != hipSuccess) return hip_fail(c, e, "job table upload");
     e = hipMemcpyAsync(S.items_dev, S.items_host, sizeof(fg_item) * nitems, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(c, e, "item map upload");
-    e = fg_launch_batch(S.dev, S.items_dev, njobs, total, total_upper, max_levels, mw1, mh1, S.counter,
-                        c->launch, s);
+    e = fg_launch_batch(S.dev, S.items_dev, njobs, total, total_upper, max_levels, mw1, mh1, all_single,
+                        S.counter, c->launch, s);
     if (e != hipSuccess) return hip_fail(c, e, "batch launch");
     rc = record_ticket(c, s, ticket);
     if (rc) return rc;
@@ -437,13 +441,15 @@ FG_API int fast_plan_create(fast_ctx *c, const fast_job *jobs, int njobs, int fl
     if (flags & ~FAST_PLAN_GRAPH) return fail(c, FAST_EINVAL, "unknown plan flags");
     std::vector<fg_job> table((size_t)(njobs > 0 ? njobs : 1));
     int total, total_upper, max_levels, mw1, mh1;
-    int rc = build_table(c, jobs, njobs, table.data(), total, total_upper, max_levels, mw1, mh1);
+    bool all_single;
+    int rc = build_table(c, jobs, njobs, table.data(), total, total_upper, max_levels, mw1, mh1, all_single);
     if (rc) return rc;
     DeviceGuard g(c->device);
     Plan p;
     p.njobs = njobs;
     p.total = total;
     p.total_upper = total_upper;
+    p.all_single = all_single;
     p.max_levels = max_levels;
     p.mw1 = mw1;
     p.mh1 = mh1;
@@ -467,7 +473,8 @@ FG_API int fast_plan_create(fast_ctx *c, const fast_job *jobs, int njobs, int fl
         if (!c->capture_stream) e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t le = fg_launch_batch(p.dev, p.items, njobs, total, total_upper, max_levels, mw1, mh1, p.counter,
+            hipError_t le = fg_launch_batch(p.dev, p.items, njobs, total, total_upper, max_levels, mw1, mh1,
+                                            all_single, p.counter,
                                             c->launch, c->capture_stream);
             e = hipStreamEndCapture(c->capture_stream, &p.graph);
             if (le != hipSuccess) e = le;
@@ -496,6 +503,7 @@ FG_API int fast_plan_launch(fast_ctx *c, int plan_id, void *stream, uint64_t *ti
     const Plan &p = c->plans[plan_id];
     hipError_t e = p.exec ? hipGraphLaunch(p.exec, s)
                           : fg_launch_batch(p.dev, p.items, p.njobs, p.total, p.total_upper, p.max_levels, p.mw1, p.mh1,
+                                            p.all_single,
                                             p.counter, c->launch, s);
     if (e != hipSuccess) return hip_fail(c, e, p.exec ? "hipGraphLaunch" : "plan launch");
     if (!ticket) return FAST_OK;

@@ -59,8 +59,12 @@ constexpr int FG_MAX_FUSED = 3;
 // fields are prefix sums.  items[0 .. total) lists every region of every job
 // once, in any order; items[total .. total + total_upper) lists every region
 // of the jobs with more than FG_MAX_FUSED levels (their deeper levels).
-// `counter` holds FG_COUNTER_WORDS zero-initialised words that the kernel
-// re-arms itself on exit.
+// all_single: every job's regions are single 64x64 sub-tiles (the pipelined
+// kernel applies).  `counter` holds FG_COUNTER_WORDS zero-initialised words
+// that the kernel re-arms itself on exit.
 hipError_t fg_launch_batch(const fg_job *jobs_dev, const fg_item *items, int njobs, int total,
-                           int total_upper, int max_levels, int max_w1, int max_h1, unsigned *counter,
-                           const fg_launch &L, hipStream_t s);
+                           int total_upper, int max_levels, int max_w1, int max_h1, bool all_single,
+                           unsigned *counter, const fg_launch &L, hipStream_t s);
+
+// Regions of at most this side (level-0 pixels) are one fused sub-tile.
+constexpr int FG_SUB = 64;
