@@ -175,7 +175,7 @@ int fast_plan_destroy(fast_ctx *ctx, int plan_id);
 /* Launch-shape tuning (the autotuner's knobs), per context.
  * region: side of the square region one workgroup owns, in level-0 pixels,
  *         rounded up to a multiple of the cell (16..256);
- * block:  threads per workgroup (64, 128, 256 or 512);
+ * block:  threads per workgroup, a multiple of 64 in 64..512;
  * persistent_blocks_per_cu: workgroups per compute unit for the persistent
  *         batched kernel (1..16).
  * Errors: FAST_EINVAL for values out of range. */

@@ -71,8 +71,8 @@ static_assert(OFF_WAVES % 16 == 0, "aligned scratch");
 
 // Per-wave scratch for V waves.  Compass rounds are dealt to the waves in
 // turn, so a wave sees at most ceil(MAX_GROUPS / 64V) rounds of 64 groups:
-// its group list holds that many words and its pixel list eight pixels per
-// group, plus one spare slot per lane.
+// its group list holds that many words (64 per round) and its pixel list
+// eight pixels per group plus one spare slot per lane.
 __host__ __device__ constexpr int blist_cap(int waves) {
     return (MAX_GROUPS + 64 * waves - 1) / (64 * waves) * 64;
 }
@@ -113,6 +113,13 @@ __device__ __forceinline__ s16x2 vmin(s16x2 a, s16x2 b) { return __builtin_eleme
 // Two bytes of the 8-byte value {hi, lo} zero-extended into 16-bit lanes.
 __device__ __forceinline__ s16x2 pair(uint32_t hi, uint32_t lo, uint32_t sel) {
     return as_s16x2(__builtin_amdgcn_perm(hi, lo, sel));
+}
+
+// floor(a / b) for 0 <= a < 2^21 and b >= 1 with the approximate reciprocal:
+// (a + 0.5) / b lies at least 0.5 / b from an integer, and the relative error
+// of rcp and of the product (< 2^-22) keeps the estimate closer than that.
+__device__ __forceinline__ int div_small(int a, int b) {
+    return (int)(((float)a + 0.5f) * __builtin_amdgcn_rcpf((float)b));
 }
 
 __device__ __forceinline__ int lane_id() {
@@ -256,42 +263,87 @@ __device__ __forceinline__ Seg make_seg(const Geo &g, bool on) {
     return q;
 }
 
-// Compass test of group i of the sub-tile's group sequence (i < total): the
-// 8-bit survivor mask, the LDS offset of the group's first pixel and its level.
+// The groups of all levels of a sub-tile form one sequence: level 0's rows
+// first, then level 1's, then level 2's.  A group's entry is the LDS offset of
+// its first pixel | level << 14, or NO_GROUP past the end.
+constexpr uint32_t NO_GROUP = 0xFFFFu;
+// Any offset whose 8 pixels and compass points lie inside the tile; a lane
+// with no group reads there and discards the result.
+constexpr uint32_t SAFE_OFF = T0 + 3 * LP + 4;
+
+struct GroupSeq {
+    int b1, b2, total;   // first group of level 1, of level 2; group count
+};
+
+__device__ __forceinline__ GroupSeq group_seq(const Seg &s0, const Seg &s1, const Seg &s2) {
+    GroupSeq q;
+    q.b1 = s0.n;
+    q.b2 = s0.n + s1.n;
+    q.total = s0.n + s1.n + s2.n;
+    return q;
+}
+
+__device__ __forceinline__ uint32_t group_entry(const Seg &s0, const Seg &s1, const Seg &s2,
+                                                const GroupSeq &q, int i) {
+    const uint32_t lvl = i < q.b1 ? 0u : (i < q.b2 ? 1u : 2u);
+    const int local = i - (lvl == 0 ? 0 : (lvl == 1 ? q.b1 : q.b2));
+    const int ppr = max(sel3(lvl, s0.ppr, s1.ppr, s2.ppr), 1);
+    // row = floor((local + 0.5) / ppr), exact with the approximate reciprocal
+    // since local < 1024 and ppr <= 9
+    const int row = (int)(((float)local + 0.5f) * __builtin_amdgcn_rcpf((float)ppr)), pp = local - row * ppr;
+    const uint32_t off = (uint32_t)(sel3(lvl, s0.tbase, s1.tbase, s2.tbase) +
+                                    (sel3(lvl, s0.r0, s1.r0, s2.r0) + row) * LP +
+                                    sel3(lvl, s0.gc0, s1.gc0, s2.gc0) + 8 * pp);
+    return i < q.total ? off | (lvl << 14) : NO_GROUP;
+}
+
+// Group entries of one lane for the (at most four) compass rounds it takes
+// when four or more waves share a sub-tile, two 16-bit entries per word.
+// Regions with the same staged geometry have the same entries, so the
+// pipelined kernel keeps them across regions; `key` names the geometry
+// (-1: not reusable).
+struct GroupCache {
+    uint32_t e01, e23;
+    int key;
+};
+
+// The words a compass test of 8 pixels reads: the 16 bytes around the group
+// on its own row (4 before, 4 after) and 8 bytes three rows above and below.
+struct Px8 {
+    uint32_t D0, D1, D2, D3, N0, N1, S0, S1;
+};
+
+__device__ __forceinline__ Px8 load8(const uint8_t *smem, uint32_t off) {
+    const uint8_t *p = smem + off;
+    Px8 x;
+    x.D0 = *(const uint32_t *)(p - 4);
+    x.D1 = *(const uint32_t *)(p);
+    x.D2 = *(const uint32_t *)(p + 4);
+    x.D3 = *(const uint32_t *)(p + 8);
+    x.N0 = *(const uint32_t *)(p - 3 * LP);
+    x.N1 = *(const uint32_t *)(p - 3 * LP + 4);
+    x.S0 = *(const uint32_t *)(p + 3 * LP);
+    x.S1 = *(const uint32_t *)(p + 3 * LP + 4);
+    return x;
+}
+
+// Compass test of the 8 pixels of x: bit j <- pixel 2j, bit 4+j <- pixel
+// 2j+1 (set = may be a corner).
 template <int K>
-__device__ __forceinline__ uint32_t compass_group(const uint8_t *smem, const Seg &s0, const Seg &s1,
-                                                  const Seg &s2, int b1, int b2, float inv0, float inv1,
-                                                  float inv2, s16x2 T1, int i, uint32_t &off,
-                                                  uint32_t &lvl) {
-    lvl = i < b1 ? 0u : (i < b2 ? 1u : 2u);
-    const int local = i - (lvl == 0 ? 0 : (lvl == 1 ? b1 : b2));
-    const int ppr = sel3(lvl, s0.ppr, s1.ppr, s2.ppr);
-    const float inv = lvl == 0 ? inv0 : (lvl == 1 ? inv1 : inv2);
-    const int row = (int)(((float)local + 0.5f) * inv), pp = local - row * ppr;
-    off = (uint32_t)(sel3(lvl, s0.tbase, s1.tbase, s2.tbase) +
-                     (sel3(lvl, s0.r0, s1.r0, s2.r0) + row) * LP + sel3(lvl, s0.gc0, s1.gc0, s2.gc0) + 8 * pp);
+__device__ __forceinline__ uint32_t compass8(const Px8 &x, s16x2 T1) {
     if constexpr (K > 0) {
-        const uint8_t *p = smem + off;
-        const uint32_t D0 = *(const uint32_t *)(p - 4);
-        const uint32_t D1 = *(const uint32_t *)(p);
-        const uint32_t D2 = *(const uint32_t *)(p + 4);
-        const uint32_t D3 = *(const uint32_t *)(p + 8);
-        const uint32_t N0 = *(const uint32_t *)(p - 3 * LP);
-        const uint32_t N1 = *(const uint32_t *)(p - 3 * LP + 4);
-        const uint32_t S0 = *(const uint32_t *)(p + 3 * LP);
-        const uint32_t S1 = *(const uint32_t *)(p + 3 * LP + 4);
         const uint32_t r01 = as_u32(compass<K>(
-            pair(D1, D1, 0x0c010c00u), pair(N0, N0, 0x0c010c00u), pair(D2, D1, 0x0c040c03u),
-            pair(S0, S0, 0x0c010c00u), pair(D1, D0, 0x0c020c01u), T1));
+            pair(x.D1, x.D1, 0x0c010c00u), pair(x.N0, x.N0, 0x0c010c00u), pair(x.D2, x.D1, 0x0c040c03u),
+            pair(x.S0, x.S0, 0x0c010c00u), pair(x.D1, x.D0, 0x0c020c01u), T1));
         const uint32_t r23 = as_u32(compass<K>(
-            pair(D1, D1, 0x0c030c02u), pair(N0, N0, 0x0c030c02u), pair(D2, D1, 0x0c060c05u),
-            pair(S0, S0, 0x0c030c02u), pair(D1, D0, 0x0c040c03u), T1));
+            pair(x.D1, x.D1, 0x0c030c02u), pair(x.N0, x.N0, 0x0c030c02u), pair(x.D2, x.D1, 0x0c060c05u),
+            pair(x.S0, x.S0, 0x0c030c02u), pair(x.D1, x.D0, 0x0c040c03u), T1));
         const uint32_t r45 = as_u32(compass<K>(
-            pair(D2, D2, 0x0c010c00u), pair(N1, N1, 0x0c010c00u), pair(D3, D2, 0x0c040c03u),
-            pair(S1, S1, 0x0c010c00u), pair(D2, D1, 0x0c020c01u), T1));
+            pair(x.D2, x.D2, 0x0c010c00u), pair(x.N1, x.N1, 0x0c010c00u), pair(x.D3, x.D2, 0x0c040c03u),
+            pair(x.S1, x.S1, 0x0c010c00u), pair(x.D2, x.D1, 0x0c020c01u), T1));
         const uint32_t r67 = as_u32(compass<K>(
-            pair(D2, D2, 0x0c030c02u), pair(N1, N1, 0x0c030c02u), pair(D3, D2, 0x0c060c05u),
-            pair(S1, S1, 0x0c030c02u), pair(D2, D1, 0x0c040c03u), T1));
+            pair(x.D2, x.D2, 0x0c030c02u), pair(x.N1, x.N1, 0x0c030c02u), pair(x.D3, x.D2, 0x0c060c05u),
+            pair(x.S1, x.S1, 0x0c030c02u), pair(x.D2, x.D1, 0x0c040c03u), T1));
         // sign bit of each 16-bit lane = rejected; bit j <- pixel 2j,
         // bit 4+j <- pixel 2j+1
         const uint32_t sg = ((r01 >> 15) & 0x10001u) | ((r23 >> 14) & 0x20002u) |
@@ -302,6 +354,12 @@ __device__ __forceinline__ uint32_t compass_group(const uint8_t *smem, const Seg
     }
 }
 
+// LDS offset a lane with entry e reads (a safe one for NO_GROUP).
+__device__ __forceinline__ uint32_t entry_off(uint32_t e) { return e != NO_GROUP ? (e & 0x3FFFu) : SAFE_OFF; }
+
+// Bits b with lo <= b < hi (0 <= lo <= hi <= 4).
+__device__ __forceinline__ uint32_t bit_range(int lo, int hi) { return (1u << hi) - (1u << lo); }
+
 // P1+P2: compass test of every scored pixel of every level, 8 pixels per
 // lane in packed 16-bit lanes.  The groups of all levels form one sequence
 // dealt to the waves round-robin in rounds of 64, so every wave does the
@@ -311,39 +369,51 @@ __device__ __forceinline__ uint32_t compass_group(const uint8_t *smem, const Seg
 // level << 22 | LDS offset of the group << 8 | survivor mask), which is then
 // expanded into the wave's pixel list, keeping testable pixels only; an entry
 // is (level << 14) | LDS offset of the pixel.  Returns the wave's pixel count.
+// With `cached` (four or more waves), the group entries are e01 and e23
+// (GroupCache).
 template <int K>
 __device__ int collect(const uint8_t *smem, const Seg &s0, const Seg &s1, const Seg &s2, int t,
-                       uint32_t *blist, uint16_t *list) {
-    const int lane = lane_id(), wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    const int total = s0.n + s1.n + s2.n;
-    const int b1 = s0.n, b2 = s0.n + s1.n;
-    // row = floor((local + 0.5) / ppr), exact with the approximate reciprocal
-    // since local < 1024 and ppr <= 9
-    const float inv0 = __builtin_amdgcn_rcpf((float)max(s0.ppr, 1)),
-                inv1 = __builtin_amdgcn_rcpf((float)max(s1.ppr, 1)),
-                inv2 = __builtin_amdgcn_rcpf((float)max(s2.ppr, 1));
+                       bool cached, uint32_t e01, uint32_t e23, uint32_t *blist, uint16_t *list) {
+    const int lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nwaves = blockDim.x >> 6;
+    const GroupSeq q = group_seq(s0, s1, s2);
     const s16x2 T1 = {(short)(t + 1), (short)(t + 1)};
     const int stride = nwaves * 64;
     int nb = 0;
-    for (int i0 = wave * 64; i0 < total; i0 += 2 * stride) {
-        const int ia = i0 + lane, ib = i0 + stride + lane;
-        uint32_t offa = 0, lvla = 0, offb = 0, lvlb = 0;
-        const uint32_t sva = ia < total ? compass_group<K>(smem, s0, s1, s2, b1, b2, inv0, inv1, inv2, T1, ia,
-                                                           offa, lvla)
-                                        : 0u;
-        const uint32_t svb = ib < total ? compass_group<K>(smem, s0, s1, s2, b1, b2, inv0, inv1, inv2, T1, ib,
-                                                           offb, lvlb)
-                                        : 0u;
-        const uint64_t bala = __ballot(sva != 0);
-        const int ranka = __builtin_amdgcn_mbcnt_hi((uint32_t)(bala >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bala, 0u));
-        if (sva) blist[nb + ranka] = (lvla << 22) | (offa << 8) | sva;
-        nb += __popcll(bala);
-        const uint64_t balb = __ballot(svb != 0);
-        const int rankb = __builtin_amdgcn_mbcnt_hi((uint32_t)(balb >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)balb, 0u));
-        if (svb) blist[nb + rankb] = (lvlb << 22) | (offb << 8) | svb;
-        nb += __popcll(balb);
+    // survivors go to nb + (survivors below the lane); the other lanes write
+    // past them, inside the round's own 64 words, where a later round
+    // overwrites them, so the stores need no branch
+    auto push = [&](uint32_t e, uint32_t sv) {
+        const uint64_t bal = __ballot(sv != 0);
+        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        const int cnt = __popcll(bal);
+        blist[sv ? nb + rank : nb + cnt + lane - rank] = (e << 8) | sv;
+        nb += cnt;
+    };
+    for (int r = 0;; r += 2) {
+        const int i0 = wave * 64 + r * stride;
+        if (i0 >= q.total) break;
+        uint32_t ea, eb;
+        if (cached) {
+            const uint32_t w = r == 0 ? e01 : e23;
+            ea = w & 0xFFFFu;
+            eb = w >> 16;
+        } else {
+            ea = group_entry(s0, s1, s2, q, i0 + lane);
+            eb = group_entry(s0, s1, s2, q, i0 + stride + lane);
+        }
+        const Px8 xa = load8(smem, entry_off(ea));
+        if (i0 + stride < q.total) {
+            // two rounds: both rounds' LDS reads are issued before either is
+            // evaluated
+            const Px8 xb = load8(smem, entry_off(eb));
+            const uint32_t sva = compass8<K>(xa, T1) & (0u - (uint32_t)(ea != NO_GROUP));
+            const uint32_t svb = compass8<K>(xb, T1) & (0u - (uint32_t)(eb != NO_GROUP));
+            push(ea, sva);
+            push(eb, svb);
+        } else {
+            push(ea, compass8<K>(xa, T1) & (0u - (uint32_t)(ea != NO_GROUP)));
+        }
     }
     wave_sync();
     int count = 0;
@@ -356,16 +426,13 @@ __device__ int collect(const uint8_t *smem, const Seg &s0, const Seg &s1, const 
         const int rel = off0 - sel3(l, s0.tbase, s1.tbase, s2.tbase);
         const int r = (int)(((uint32_t)rel * 18725u) >> 21);   // rel / LP
         const int c0 = rel - r * LP;
-        const int c_lo = sel3(l, s0.c_lo, s1.c_lo, s2.c_lo), c_hi = sel3(l, s0.c_hi, s1.c_hi, s2.c_hi);
         const bool row_ok = r >= sel3(l, s0.r_lo, s1.r_lo, s2.r_lo) && r <= sel3(l, s0.r_hi, s1.r_hi, s2.r_hi);
-        // bit b of the mask is pixel q(b) = 2 (b & 3) + (b >> 2) of the group
-        uint32_t m = 0;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const int c = c0 + (((b & 3) << 1) | (b >> 2));
-            m |= (row_ok && c >= c_lo && c <= c_hi ? 1u : 0u) << b;
-        }
-        m &= w;
+        // pixel p of the group (column c0 + p) is testable iff lo <= p < hi;
+        // bit b of the mask is pixel 2b (b < 4) or 2(b-4)+1
+        const int lo = min(max(sel3(l, s0.c_lo, s1.c_lo, s2.c_lo) - c0, 0), 8);
+        const int hi = max(min(max(sel3(l, s0.c_hi, s1.c_hi, s2.c_hi) - c0 + 1, 0), 8), lo);
+        const uint32_t valid = bit_range((lo + 1) >> 1, (hi + 1) >> 1) | (bit_range(lo >> 1, hi >> 1) << 4);
+        const uint32_t m = row_ok ? (w & valid) : 0u;
         const int cnt = __builtin_popcount(m);
         const int incl = wave_scan(cnt);
         const int pos = count + incl - cnt;
@@ -381,6 +448,17 @@ __device__ int collect(const uint8_t *smem, const Seg &s0, const Seg &s1, const 
     }
     return count;
 }
+
+// Entries of this lane's compass rounds when at least four waves share the
+// sub-tile (at most four rounds: MAX_GROUPS <= 4 * 256).
+__device__ __forceinline__ void group_cache_fill(GroupCache &c, const Seg &s0, const Seg &s1, const Seg &s2) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6, stride = (blockDim.x >> 6) * 64;
+    const GroupSeq q = group_seq(s0, s1, s2);
+    const int i = wave * 64 + lane;
+    c.e01 = group_entry(s0, s1, s2, q, i) | (group_entry(s0, s1, s2, q, i + stride) << 16);
+    c.e23 = group_entry(s0, s1, s2, q, i + 2 * stride) | (group_entry(s0, s1, s2, q, i + 3 * stride) << 16);
+}
+static_assert(MAX_GROUPS <= 4 * 256, "four compass rounds per wave with four or more waves");
 
 // P3: keep entries that pass the 8-point test, compacted in place.
 __device__ int pass_even8(const uint8_t *smem, int t, int k8, uint16_t *list, int n1) {
@@ -461,9 +539,14 @@ struct NoHook {
 // scoring from NMS, `after` just after it (the pipelined kernel uses them to
 // publish its next work item and to reuse the level-0 tile, which NMS no
 // longer reads).
+//
+// `cache` (workgroups of four or more waves only) keeps the compass group
+// entries across calls whose staged geometry has the same `cache_key`
+// (-1: recompute).
 template <class Before = NoHook, class After = NoHook>
 __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Geo &g2, int nl,
-                           const Params &P, uint32_t *keys, Before before = Before(), After after = After()) {
+                           const Params &P, uint32_t *keys, GroupCache *cache = nullptr, int cache_key = -1,
+                           Before before = Before(), After after = After()) {
     const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     uint8_t *scratch = smem + OFF_WAVES + wave * wave_bytes(nwaves);
     uint32_t *blist = (uint32_t *)scratch;
@@ -471,13 +554,18 @@ __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Ge
     const Seg s0 = make_seg(g0, has_area(g0));
     const Seg s1 = make_seg(g1, nl > 1 && has_area(g1));
     const Seg s2 = make_seg(g2, nl > 2 && has_area(g2));
+    if (cache && (cache_key < 0 || __builtin_amdgcn_readfirstlane(cache->key) != cache_key)) {
+        group_cache_fill(*cache, s0, s1, s2);
+        cache->key = cache_key;
+    }
+    const uint32_t ce01 = cache ? cache->e01 : 0u, ce23 = cache ? cache->e23 : 0u;
     int n1 = 0;
     switch (P.kc) {
-        case 0: n1 = collect<0>(smem, s0, s1, s2, P.t, blist, list); break;
-        case 1: n1 = collect<1>(smem, s0, s1, s2, P.t, blist, list); break;
-        case 2: n1 = collect<2>(smem, s0, s1, s2, P.t, blist, list); break;
-        case 3: n1 = collect<3>(smem, s0, s1, s2, P.t, blist, list); break;
-        default: n1 = collect<4>(smem, s0, s1, s2, P.t, blist, list); break;
+        case 0: n1 = collect<0>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
+        case 1: n1 = collect<1>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
+        case 2: n1 = collect<2>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
+        case 3: n1 = collect<3>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
+        default: n1 = collect<4>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
     }
     wave_sync();
     const int n2 = pass_even8(smem, P.t, P.k8, list, n1);
@@ -547,11 +635,15 @@ __device__ __forceinline__ void tile_issue(TileRegs &R, const uint8_t *img, int 
     const int gx = tx + 16 * ch;
     const bool col_ok = ch < (tw >> 4) && gx >= 0 && gx < P;
     const int r0 = threadIdx.x >> 3, dr = blockDim.x >> 3;
+    // row pointers advance by a uniform stride: one 64-bit multiply per thread
+    const uint8_t *row = img + (ptrdiff_t)(ty + r0) * P + gx;
+    const ptrdiff_t step = (ptrdiff_t)dr * P;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int r = r0 + j * dr, gy = ty + r;
         R.v[j] = u32x4{0u, 0u, 0u, 0u};
-        if (r < th && col_ok && gy >= 0 && gy < H) R.v[j] = gload<u32x4>(img + (size_t)gy * P + gx);
+        if (r < th && col_ok && gy >= 0 && gy < H) R.v[j] = gload<u32x4>(row);
+        row += step;
     }
 }
 
@@ -600,7 +692,7 @@ __device__ void halve_two(const uint8_t *l0, uint8_t *l1, uint8_t *l2, int tw, i
     const int wpr = tw >> 4, rows2 = th >> 2;
     const int tasks = wpr * rows2 + (((th >> 1) & 1) ? wpr : 0);
     for (int i = threadIdx.x; i < tasks; i += blockDim.x) {
-        const int y2 = i / wpr, x4 = i - y2 * wpr;
+        const int y2 = div_small(i, wpr), x4 = i - y2 * wpr;
         const uint8_t *s = l0 + (4 * y2) * LP + 16 * x4;
         if (y2 < rows2) {
             const u32x4 a = *(const u32x4 *)s, b = *(const u32x4 *)(s + LP);
@@ -771,8 +863,8 @@ struct Region {
 
 __device__ __forceinline__ Region region_of(const fg_job &J, int region) {
     Region R;
-    R.rxi = region % J.rx;
-    R.ryi = region / J.rx;
+    R.ryi = region < (1 << 21) ? div_small(region, J.rx) : region / J.rx;
+    R.rxi = region - R.ryi * J.rx;
     R.ncx = min(J.rcells, J.gw - R.rxi * J.rcells);
     R.ncy = min(J.rcells, J.gh - R.ryi * J.rcells);
     R.P.t = J.t;
@@ -795,7 +887,8 @@ __device__ __forceinline__ void keys_clear(uint32_t *keys, int n) {
 // Decode the region's cell keys into output slots.
 __device__ void keys_write(const fg_job &J, const Region &R, const uint32_t *keys) {
     for (int i = threadIdx.x; i < R.ncx * R.ncy; i += blockDim.x) {
-        const int cx = R.rxi * J.rcells + i % R.ncx, cy = R.ryi * J.rcells + i / R.ncx;
+        const int qy = div_small(i, R.ncx);   // i < MAX_KEYS
+        const int cx = R.rxi * J.rcells + i - qy * R.ncx, cy = R.ryi * J.rcells + qy;
         const uint32_t key = keys[i];
         // fast_feature {x, y, score, level, reserved} as one little-endian word
         uint64_t f;
@@ -805,8 +898,9 @@ __device__ void keys_write(const fg_job &J, const Region &R, const uint32_t *key
             const int level = 7 - (int)((key >> 16) & 7u);
             const uint32_t local = 0xFFFFu - (key & 0xFFFFu);
             const int cw = J.cell >> level;
-            const uint32_t x = (uint32_t)(((cx * J.cell) >> level) + (int)(local % (uint32_t)cw));
-            const uint32_t y = (uint32_t)(((cy * J.cell) >> level) + (int)(local / (uint32_t)cw));
+            const int ly = div_small((int)local, cw);   // local < cw * cw <= 2^16
+            const uint32_t x = (uint32_t)(((cx * J.cell) >> level) + (int)local - ly * cw);
+            const uint32_t y = (uint32_t)(((cy * J.cell) >> level) + ly);
             f = (uint64_t)(x | (y << 16)) | ((uint64_t)(key >> 19) << 32) | ((uint64_t)level << 48);
         }
         gstore<uint64_t>(J.out + (size_t)cy * J.gw + cx, f);
@@ -829,7 +923,8 @@ __device__ void detect_region(const fg_job &J, int region, uint8_t *smem) {
 // of keys_write).
 __device__ void keys_from_slots(const fg_job &J, const Region &R, uint32_t *keys) {
     for (int i = threadIdx.x; i < R.ncx * R.ncy; i += blockDim.x) {
-        const int cx = R.rxi * J.rcells + i % R.ncx, cy = R.ryi * J.rcells + i / R.ncx;
+        const int qy = div_small(i, R.ncx);
+        const int cx = R.rxi * J.rcells + i - qy * R.ncx, cy = R.ryi * J.rcells + qy;
         const uint64_t f = gload<uint64_t>(J.out + (size_t)cy * J.gw + cx);
         const uint32_t score = (uint32_t)(f >> 32) & 0xFFFFu;
         uint32_t key = 0;
@@ -922,7 +1017,7 @@ __device__ __forceinline__ void queue_exit(unsigned *counter) {
 //   [C] the scores are complete and the tile is no longer read: commit the
 //       next region's tile (loaded into registers one region earlier) to
 //       LDS, start loading the tile after it, then run NMS into the keys.
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8)))
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4)))
 detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__ items, int total,
                     unsigned *counter) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -947,6 +1042,7 @@ detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__
     fg_item prev{0u, 0u};
     bool have_prev = false;
     int b = 0;
+    GroupCache gcache{0u, 0u, -1};
     while (item < total) {
         const fg_job &J = jobs[il.job];   // uniform: read through the scalar cache
         const Region R = region_of(J, (int)il.region);
@@ -964,8 +1060,13 @@ detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__
         unsigned ticket = 0;
         if (threadIdx.x == 0 && next < total) ticket = atomicAdd(&counter[0], 1u);
         int after = total;
+        // the staged geometry depends only on the fused level count and the
+        // region's size once its origin is 16-aligned across and 4-aligned down
+        const int gkey = (R.P.rx0 & 15) == 0 && (R.P.ry0 & 3) == 0
+                             ? fused_levels(J) | (R.xr1 - R.P.rx0) << 2 | (R.yr1 - R.P.ry0) << 9
+                             : -1;
         run_passes(
-            smem, g0, g1, g2, fused_levels(J), R.P, keys,
+            smem, g0, g1, g2, fused_levels(J), R.P, keys, &gcache, gkey,
             [&]() {
                 if (threadIdx.x == 0) {
                     const unsigned cand = 2u * (unsigned)G + ticket;

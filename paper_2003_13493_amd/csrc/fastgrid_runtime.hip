@@ -312,8 +312,8 @@ FG_API int fast_grid_dims(int width, int height, int cell, int *gw, int *gh) {
 FG_API int fast_set_launch(fast_ctx *c, int region, int block, int bpc) {
     if (!c) return FAST_EINVAL;
     if (region < 16 || region > 256) return fail(c, FAST_EINVAL, "region not in 16..256");
-    if (block != 64 && block != 128 && block != 256 && block != 512)
-        return fail(c, FAST_EINVAL, "block not one of 64,128,256,512");
+    if (block < 64 || block > 512 || block % 64 != 0)
+        return fail(c, FAST_EINVAL, "block not a multiple of 64 in 64..512");
     if (bpc < 1 || bpc > 16) return fail(c, FAST_EINVAL, "blocks per CU not in 1..16");
     c->launch.region = region;
     c->launch.block = block;

@@ -25,6 +25,7 @@ CANDIDATES = [
     (64, 256, 2), (64, 256, 3), (64, 256, 4),
     (64, 512, 1), (64, 512, 2),
     (64, 128, 4), (64, 128, 6), (128, 256, 3), (128, 512, 2), (32, 256, 3), (32, 256, 4),
+    (64, 320, 3), (64, 384, 2), (64, 448, 2), (128, 320, 3),
 ]
 
 

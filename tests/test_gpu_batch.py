@@ -182,8 +182,9 @@ def test_poll_unknown_ticket(ctx):
         ctx.poll(10 ** 12)
 
 
-@pytest.mark.parametrize("shape", [(64, 256, 3), (128, 256, 3), (256, 512, 2), (32, 128, 4)],
-                         ids=["r64", "r128", "r256", "r32_b128"])
+@pytest.mark.parametrize("shape", [(64, 256, 3), (128, 256, 3), (256, 512, 2), (32, 128, 4),
+                                   (64, 320, 3), (64, 448, 2), (128, 192, 4)],
+                         ids=["r64", "r128", "r256", "r32_b128", "r64_b320", "r64_b448", "r128_b192"])
 def test_batch_launch_shapes_with_deep_levels(ctx, shape):
     """The persistent kernel with regions of several sub-tiles (no register
     prefetch), small workgroups, and jobs of 1..5 levels, so the fused pass
