@@ -143,6 +143,36 @@ def test_plan_mixed_levels(ctx, graph):
         ctx.plan_destroy(pid)
 
 
+def test_batch_single_subtile_regions_of_mixed_sides(ctx):
+    """Cells of 16, 24, 32, 48 and 64 pixels give single-sub-tile regions 48 or
+    64 pixels wide (plus clipped ones at frame edges) with 1..3 levels in one
+    launch, so the pipelined kernel changes staged geometry from region to
+    region and must not reuse compass group entries across geometries."""
+    rng = np.random.default_rng(123)
+    specs, frames, want = [], [], []
+    for i in range(15):
+        levels = 1 + i % 3
+        cell = (16, 24, 32, 48, 64)[i % 5]
+        w = int(rng.integers(40, 420))
+        h = int(rng.integers(30, 300))
+        s = synth.FrameSpec(w, h, levels, synth.BATCH_T[i % 4], synth.BATCH_N[i % 3], cell,
+                            seed=1300 + i, nshapes=50, sigma=4.0)
+        img = s.make()
+        specs.append(s)
+        frames.append(img)
+        slots, planes = oracle.detect_grid(img, w, levels, s.t, s.n, cell)
+        want.append((slots, [p[:, :pw].copy() for p, pw in planes]))
+    print("case batch mixed region sides", flush=True)
+    pyrs, grids, jobs = make_resident(specs, frames)
+    for r in range(2):
+        for g in grids:
+            g.tensor.fill_(0x77)
+        torch.cuda.synchronize()
+        tk = ctx.submit(jobs)
+        assert ctx.wait(tk, 60_000)
+        check_all(specs, pyrs, grids, want, f"mixed sides round {r}")
+
+
 def test_plan_rejects_unknown_flags(ctx, batch):
     specs, frames, _ = batch
     pyrs, grids, jobs = make_resident(specs[:2], frames[:2])
