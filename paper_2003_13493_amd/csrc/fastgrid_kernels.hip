@@ -187,28 +187,25 @@ __device__ __forceinline__ s16x2 compass(s16x2 C, s16x2 N, s16x2 E, s16x2 S, s16
 constexpr int CDX[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
 constexpr int CDY[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
 
-// Full segment test and score (Eq. (1)) of the pixel at p.  Sums use
-// max(x,0) = (x + |x|)/2 over the whole circle.
+// Full segment test and score (Eq. (1)) of the pixel at p.  The sums
+// accumulate max(v - (c+t), 0) and max((c-t) - v, 0), each one saturating
+// unsigned subtraction.
 __device__ __forceinline__ uint32_t full_score(const uint8_t *p, int t, int n) {
-    const int cv = p[0];
-    const int hi = cv + t;
-    const int lo = cv - t > 0 ? cv - t : 0;   // darker needs v < c-t; none if c-t <= 0
-    uint32_t bm = 0, dm = 0;
-    int sum = 0, ab = 0, ad = 0;
+    const uint32_t cv = p[0];
+    const uint32_t hi = cv + (uint32_t)t;
+    const uint32_t lo = (int)cv - t > 0 ? cv - (uint32_t)t : 0u;   // darker needs v < c-t; none if c-t <= 0
+    uint32_t bm = 0, dm = 0, sb = 0, sd = 0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        const int v = p[CIRC(j)];
-        bm = __builtin_amdgcn_alignbit(bm, (uint32_t)(hi - v), 31);
-        dm = __builtin_amdgcn_alignbit(dm, (uint32_t)(v - lo), 31);
-        sum += v;
-        ab += v > hi ? v - hi : hi - v;
-        ad += v > lo ? v - lo : lo - v;
+        const uint32_t v = p[CIRC(j)];
+        bm = __builtin_amdgcn_alignbit(bm, hi - v, 31);   // sign: v > c+t
+        dm = __builtin_amdgcn_alignbit(dm, v - lo, 31);   // sign: v < c-t
+        sb += __builtin_elementwise_sub_sat(v, hi);
+        sd += __builtin_elementwise_sub_sat(lo, v);
     }
     const uint32_t b2 = bm | (bm << 16), d2 = dm | (dm << 16);
     if (((runs(b2, n) | runs(d2, n)) & 0xFFFFu) == 0) return 0;
-    const int sb = (sum - 16 * hi + ab) >> 1;
-    const int sd = (16 * lo - sum + ad) >> 1;
-    return (uint32_t)(sb > sd ? sb : sd);
+    return sb > sd ? sb : sd;
 }
 
 // One pyramid level of the current sub-tile as staged in LDS (uniform).
