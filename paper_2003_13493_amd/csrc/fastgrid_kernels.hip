@@ -769,12 +769,9 @@ __device__ __forceinline__ Stage fused_stage(const fg_job &J, int sx0, int sy0, 
     return st;
 }
 
-// With level 0 of a fused sub-tile in LDS: build levels 1.. in LDS, describe
-// every level, and write levels 1.. of the sub-tile to their planes.
-// sync_first: a barrier must separate the level-0 tile's commit from the
-// halving (the pipelined kernel has one already).
-__device__ void build_fused(const fg_job &J, int sx0, int sy0, int xr1, int yr1, const Stage &st,
-                            uint8_t *smem, Geo &g0, Geo &g1, Geo &g2, bool sync_first = true) {
+// Describe levels 0 .. F-1 of a fused sub-tile staged as `st`.
+__device__ void describe_fused(const fg_job &J, int sx0, int sy0, int xr1, int yr1, const Stage &st, Geo &g0,
+                               Geo &g1, Geo &g2) {
     level_area(J, 0, sx0, sy0, xr1, yr1, g0);
     g0.tbase = T0;
     g0.tx = st.tx;
@@ -786,8 +783,6 @@ __device__ void build_fused(const fg_job &J, int sx0, int sy0, int xr1, int yr1,
     g2 = g0;
     const int nl = fused_levels(J);
     if (nl > 1) {
-        if (sync_first) __syncthreads();
-        halve_two(smem + T0, smem + T1, smem + T2, st.tw, st.th, nl > 2);
         level_area(J, 1, sx0, sy0, xr1, yr1, g1);
         g1.tbase = T1;
         g1.tx = st.tx >> 1;
@@ -804,6 +799,18 @@ __device__ void build_fused(const fg_job &J, int sx0, int sy0, int xr1, int yr1,
         g2.moff = OFF_M2;
         g2.mp = M2_P;
         set_groups(g2);
+    }
+}
+
+// With level 0 of a fused sub-tile in LDS: build levels 1.. in LDS, describe
+// every level, and write levels 1.. of the sub-tile to their planes.
+__device__ void build_fused(const fg_job &J, int sx0, int sy0, int xr1, int yr1, const Stage &st,
+                            uint8_t *smem, Geo &g0, Geo &g1, Geo &g2) {
+    describe_fused(J, sx0, sy0, xr1, yr1, st, g0, g1, g2);
+    const int nl = fused_levels(J);
+    if (nl > 1) {
+        __syncthreads();
+        halve_two(smem + T0, smem + T1, smem + T2, st.tw, st.th, nl > 2);
     }
     __syncthreads();
     if (nl > 1 && has_area(g1))
@@ -949,11 +956,84 @@ __device__ void detect_region_upper(const fg_job &J, int region, uint8_t *smem) 
     keys_write(J, R, keys);
 }
 
+// Tile staging of the pipelined kernel: thread i owns the 16-byte chunk
+// column i % 8 of level-0 tile rows 4(i/8) .. 4(i/8)+3 (workgroups of at
+// least 256 threads cover a fused tile), so it holds whole 16 x 4 blocks and
+// builds the 8 x 2 level-1 and 4 x 1 level-2 pixels they cover in registers.
+__device__ __forceinline__ void quad_issue(TileRegs &R, const uint8_t *img, int H, int P, const Stage &st) {
+    const int ch = threadIdx.x & 7, q = threadIdx.x >> 3;
+    const int gx = st.tx + 16 * ch;
+    const bool ok = ch < (st.tw >> 4) && 4 * q < st.th && gx >= 0 && gx < P;
+    const uint8_t *row = img + (ptrdiff_t)(st.ty + 4 * q) * P + gx;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int gy = st.ty + 4 * q + j;
+        R.v[j] = u32x4{0u, 0u, 0u, 0u};
+        if (ok && 4 * q + j < st.th && gy >= 0 && gy < H) R.v[j] = gload<u32x4>(row);
+        row += P;
+    }
+}
+
+// Write the n-pixel piece w (n = 4 or 8, little-endian) of row y of a plane,
+// starting at column x (a multiple of n), clipped to [sx, ex) x [sy, ey).
+__device__ __forceinline__ void store_piece(uint8_t *plane, int P, int y, int x, uint64_t w, int n,
+                                            const Geo &g) {
+    if (y < g.sy || y >= g.ey || x + n <= g.sx || x >= g.ex) return;
+    uint8_t *d = plane + (ptrdiff_t)y * P + x;
+    if (x >= g.sx && x + n <= g.ex) {
+        if (n == 8)
+            gstore<uint64_t>(d, w);
+        else
+            gstore<uint32_t>(d, (uint32_t)w);
+    } else {
+        for (int i = 0; i < n; ++i)
+            if (x + i >= g.sx && x + i < g.ex) gstore<uint8_t>(d + i, (uint8_t)(w >> (8 * i)));
+    }
+}
+
+// Commit a quad-staged level-0 tile to LDS, build levels 1 and 2 of it into
+// LDS from registers (rows past the tile are zero and only feed level rows
+// past the level tile, which nothing reads), and write the sub-tile's own
+// level-1 and level-2 pixels to their planes.
+__device__ void quad_commit(uint8_t *smem, const TileRegs &R, const Stage &st, const fg_job &J, const Geo &g1,
+                            const Geo &g2) {
+    const int ch = threadIdx.x & 7, q = threadIdx.x >> 3;
+    if (ch >= (st.tw >> 4) || 4 * q >= st.th) return;
+    uint8_t *t0 = smem + T0 + 4 * q * LP + 16 * ch;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (4 * q + j < st.th) *(u32x4 *)(t0 + j * LP) = R.v[j];
+    const int nl = fused_levels(J);
+    if (nl < 2) return;
+    const u32x4 a = R.v[0], b = R.v[1], c = R.v[2], d = R.v[3];
+    const uint32_t r0a = halve4(make_uint2(a.x, a.y), make_uint2(b.x, b.y));
+    const uint32_t r0b = halve4(make_uint2(a.z, a.w), make_uint2(b.z, b.w));
+    const uint32_t r1a = halve4(make_uint2(c.x, c.y), make_uint2(d.x, d.y));
+    const uint32_t r1b = halve4(make_uint2(c.z, c.w), make_uint2(d.z, d.w));
+    *(uint2 *)(smem + T1 + (2 * q) * LP + 8 * ch) = make_uint2(r0a, r0b);
+    *(uint2 *)(smem + T1 + (2 * q + 1) * LP + 8 * ch) = make_uint2(r1a, r1b);
+    const int x1 = (st.tx >> 1) + 8 * ch, y1 = (st.ty >> 1) + 2 * q;
+    store_piece(J.lvl[1], J.pitch[1], y1, x1, (uint64_t)r0b << 32 | r0a, 8, g1);
+    store_piece(J.lvl[1], J.pitch[1], y1 + 1, x1, (uint64_t)r1b << 32 | r1a, 8, g1);
+    if (nl < 3) return;
+    const uint32_t l2 = halve4(make_uint2(r0a, r0b), make_uint2(r1a, r1b));
+    *(uint32_t *)(smem + T2 + q * LP + 4 * ch) = l2;
+    store_piece(J.lvl[2], J.pitch[2], (st.ty >> 2) + q, (st.tx >> 2) + 4 * ch, l2, 4, g2);
+}
+
 // Issue the level-0 tile loads of a single-fused-sub-tile region.
 __device__ __forceinline__ void region_prefetch(const fg_job &J, int region, TileRegs &T) {
     const Region R = region_of(J, region);
+    quad_issue(T, J.lvl[0], J.h[0], J.pitch[0], fused_stage(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1));
+}
+
+// Commit a prefetched region's tile and build its levels 1-2 (quad_commit).
+__device__ __forceinline__ void region_commit(uint8_t *smem, const fg_job &J, int region, const TileRegs &T) {
+    const Region R = region_of(J, region);
     const Stage st = fused_stage(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1);
-    tile_issue(T, J.lvl[0], J.h[0], J.pitch[0], st.tx, st.ty, st.tw, st.th);
+    Geo g0, g1, g2;
+    describe_fused(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1, st, g0, g1, g2);
+    quad_commit(smem, T, st, J, g1, g2);
 }
 
 // Bijective block -> item map that gives each XCD (blocks are dealt to the 8
@@ -1003,17 +1083,18 @@ __device__ __forceinline__ void queue_exit(unsigned *counter) {
 }
 
 // Pipelined kernel, for batches whose regions are all single fused sub-tiles
-// and workgroups of at least 256 threads (four tile rows per thread cover a
+// and workgroups of at least 256 threads (32 quads of tile rows cover a
 // fused tile).  Per region there are three workgroup barriers:
-//   [A] the previous region's NMS is done and this region's level-0 tile is
-//       in LDS: write the previous region's slots, clear the score maps and
-//       this region's cell keys (two key buffers alternate), build levels
-//       1-2 in LDS;
-//   [B] write levels 1-2, draw the ticket of the region after next, run the
-//       compass, 8-point and scoring passes; thread 0 resolves the ticket;
-//   [C] the scores are complete and the tile is no longer read: commit the
-//       next region's tile (loaded into registers one region earlier) to
-//       LDS, start loading the tile after it, then run NMS into the keys.
+//   [A] the previous region's NMS is done; this region's levels 0-2 are in
+//       LDS: write the previous region's slots, clear the score maps and
+//       this region's cell keys (two key buffers alternate);
+//   [B] draw the ticket of the region after next, run the compass, 8-point
+//       and scoring passes; thread 0 resolves the ticket;
+//   [C] the scores are complete and the tiles are no longer read: commit
+//       the next region's level-0 tile (loaded into registers one region
+//       earlier) to LDS, build its levels 1-2 from the registers into LDS
+//       and their planes, start loading the tile after it, then run NMS into
+//       the keys.
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4)))
 detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__ items, int total,
                     unsigned *counter) {
@@ -1028,14 +1109,9 @@ detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__
     fg_item il = items[item];
     fg_item in = next < total ? items[next] : fg_item{0u, 0u};
     TileRegs T;
-    {
-        const fg_job &J = jobs[il.job];
-        const Region R = region_of(J, (int)il.region);
-        const Stage st = fused_stage(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1);
-        region_prefetch(J, (int)il.region, T);
-        tile_commit(smem + T0, T, st.tw, st.th);
-        if (next < total) region_prefetch(jobs[in.job], (int)in.region, T);
-    }
+    region_prefetch(jobs[il.job], (int)il.region, T);
+    region_commit(smem, jobs[il.job], (int)il.region, T);
+    if (next < total) region_prefetch(jobs[in.job], (int)in.region, T);
     fg_item prev{0u, 0u};
     bool have_prev = false;
     int b = 0;
@@ -1053,7 +1129,8 @@ detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__
         zero_lds(smem + OFF_M0, OFF_KEYS - OFF_M0);
         keys_clear(keys, R.ncx * R.ncy);
         Geo g0, g1, g2;
-        build_fused(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1, st, smem, g0, g1, g2, false);   // ends with [B]
+        describe_fused(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1, st, g0, g1, g2);
+        __syncthreads();   // [B]
         unsigned ticket = 0;
         if (threadIdx.x == 0 && next < total) ticket = atomicAdd(&counter[0], 1u);
         int after = total;
@@ -1073,10 +1150,7 @@ detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__
             [&]() {   // after [C]
                 after = __builtin_amdgcn_readfirstlane(s_next[b]);
                 if (next < total) {
-                    const fg_job &Jn = jobs[in.job];
-                    const Region Rn = region_of(Jn, (int)in.region);
-                    const Stage sn = fused_stage(Jn, Rn.P.rx0, Rn.P.ry0, Rn.xr1, Rn.yr1);
-                    tile_commit(smem + T0, T, sn.tw, sn.th);
+                    region_commit(smem, jobs[in.job], (int)in.region, T);
                     if (after < total) {
                         const fg_item ia = items[after];
                         region_prefetch(jobs[ia.job], (int)ia.region, T);
