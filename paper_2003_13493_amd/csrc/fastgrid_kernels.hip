@@ -565,6 +565,10 @@ __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Ge
         default: n1 = collect<4>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
     }
     wave_sync();
+    // the later passes run at a raised wave priority: a wave that is further
+    // through its sub-tile issues first, so workgroups reach their barriers
+    // sooner (the waves sharing a SIMD belong to different workgroups)
+    __builtin_amdgcn_s_setprio(1);
     const int n2 = pass_even8(smem, P.t, P.k8, list, n1);
     const LevelMap m0 = level_map(g0, 0, T0, g0.sy, g0.ey, P);
     const LevelMap m1 = level_map(g1, 96, T1 - 96 * LP, g1.sy, g1.ey, P);
@@ -615,6 +619,7 @@ __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Ge
         const uint32_t key = (s << 19) | ((uint32_t)(7 - (g0.k + l)) << 16) | (0xFFFFu - local);
         atomicMax(&keys[cy * P.ncx + cx], key);
     }
+    __builtin_amdgcn_s_setprio(0);
 }
 
 // Stage level pixels [tx, tx+tw) x [ty, ty+th) into an LDS tile with 16-byte
