@@ -135,8 +135,9 @@ int fast_detect_grid(fast_ctx *ctx, const fast_plane *pyr, int levels, int t, in
 
 /* Batched path: all `njobs` requests (1..FAST_MAX_JOBS, any mix of sizes and
  * parameters) run in one persistent launch fed by a device-side work queue.
- * The job table is copied to the device before return-free enqueue on
- * `stream`; *ticket identifies the submission for fast_poll / fast_wait.
+ * The job table and its work-item list are enqueued on `stream` as one copy
+ * from library-owned pinned memory, followed by the kernels; nothing blocks.
+ * *ticket identifies the submission for fast_poll / fast_wait.
  * Each job is validated like fast_detect_grid; one bad job rejects the whole
  * submission with FAST_EINVAL and nothing is enqueued.  FAST_EBUSY if the
  * context's in-flight table slots are all taken by unfinished submissions. */
@@ -148,7 +149,8 @@ int fast_submit(fast_ctx *ctx, const fast_job *jobs, int njobs, void *stream,
 int fast_poll(fast_ctx *ctx, uint64_t ticket);
 
 /* Block until the submission finishes or timeout_ms passes (timeout_ms < 0:
- * no limit).  Returns FAST_OK, FAST_ETIMEDOUT, or an error. */
+ * no limit).  Polls without sleeping for the first 2 ms, then every 20 us.
+ * Returns FAST_OK, FAST_ETIMEDOUT, or an error. */
 int fast_wait(fast_ctx *ctx, uint64_t ticket, int timeout_ms);
 
 /* A resident batch: the job table is uploaded once into context-owned device

@@ -3,6 +3,7 @@
 // batches.  See include/fastgrid.h for the contract of every entry point.
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <mutex>
 #include <string>
@@ -22,15 +23,18 @@ namespace {
 constexpr int TICKET_RING = 256;   // submissions tracked per context
 constexpr int TABLE_SLOTS = 8;     // job tables that may be in flight at once
 
+// A submission's job table and work items travel in one host-to-device copy:
+// the jobs at offset 0 and the items from items_offset(njobs), in a pinned
+// staging buffer and its device twin of `cap` bytes.
 struct TableSlot {
-    fg_job *host = nullptr;        // pinned staging copy
-    fg_job *dev = nullptr;
+    uint8_t *host = nullptr;       // pinned staging buffer
+    uint8_t *dev = nullptr;
+    size_t cap = 0;
     unsigned *counter = nullptr;   // persistent-queue counters (FG_COUNTER_WORDS)
-    fg_item *items_host = nullptr;   // pinned work-item table
-    fg_item *items_dev = nullptr;
-    int items_cap = 0;
     uint64_t ticket = 0;           // last submission that used this slot
 };
+
+size_t items_offset(int njobs) { return (sizeof(fg_job) * (size_t)njobs + 15) & ~(size_t)15; }
 
 struct Plan {
     bool live = false;
@@ -276,8 +280,6 @@ FG_API void fast_ctx_destroy(fast_ctx *c) {
         if (s.host) (void)hipHostFree(s.host);
         if (s.dev) (void)hipFree(s.dev);
         if (s.counter) (void)hipFree(s.counter);
-        if (s.items_host) (void)hipHostFree(s.items_host);
-        if (s.items_dev) (void)hipFree(s.items_dev);
     }
     for (auto &e : c->events)
         if (e) (void)hipEventDestroy(e);
@@ -370,10 +372,12 @@ FG_API int fast_submit(fast_ctx *c, const fast_job *jobs, int njobs, void *strea
     DeviceGuard g(c->device);
     TableSlot &S = c->slots[slot];
     if (!S.host) {
-        hipError_t e = hipHostMalloc((void **)&S.host, sizeof(fg_job) * FAST_MAX_JOBS, hipHostMallocDefault);
+        const size_t cap = items_offset(FAST_MAX_JOBS) + sizeof(fg_item) * 65536;
+        hipError_t e = hipHostMalloc((void **)&S.host, cap, hipHostMallocDefault);
         if (e != hipSuccess) { S.host = nullptr; return hip_fail(c, e, "hipHostMalloc job table"); }
-        e = hipMalloc((void **)&S.dev, sizeof(fg_job) * FAST_MAX_JOBS);
+        e = hipMalloc((void **)&S.dev, cap);
         if (e != hipSuccess) { S.dev = nullptr; return hip_fail(c, e, "hipMalloc job table"); }
+        S.cap = cap;
         e = hipMalloc((void **)&S.counter, FG_COUNTER_WORDS * sizeof(unsigned));
         if (e != hipSuccess) { S.counter = nullptr; return hip_fail(c, e, "hipMalloc counter"); }
         e = hipMemset(S.counter, 0, FG_COUNTER_WORDS * sizeof(unsigned));
@@ -381,30 +385,36 @@ FG_API int fast_submit(fast_ctx *c, const fast_job *jobs, int njobs, void *strea
     }
     int total, total_upper, max_levels, mw1, mh1;
     bool all_single;
-    int rc = build_table(c, jobs, njobs, S.host, total, total_upper, max_levels, mw1, mh1, all_single);
+    // the staging buffer always has room for FAST_MAX_JOBS jobs
+    int rc = build_table(c, jobs, njobs, (fg_job *)S.host, total, total_upper, max_levels, mw1, mh1, all_single);
     if (rc) return rc;
     const int nitems = total + total_upper;
-    if (nitems > S.items_cap) {
-        // the slot is idle, so its old map is no longer read by the device
-        if (S.items_host) (void)hipHostFree(S.items_host);
-        if (S.items_dev) (void)hipFree(S.items_dev);
-        S.items_host = nullptr;
-        S.items_dev = nullptr;
-        S.items_cap = 0;
-        const int cap = nitems > 65536 ? nitems : 65536;
-        hipError_t e = hipHostMalloc((void **)&S.items_host, sizeof(fg_item) * cap, hipHostMallocDefault);
-        if (e != hipSuccess) { S.items_host = nullptr; return hip_fail(c, e, "hipHostMalloc item map"); }
-        e = hipMalloc((void **)&S.items_dev, sizeof(fg_item) * cap);
-        if (e != hipSuccess) { S.items_dev = nullptr; return hip_fail(c, e, "hipMalloc item map"); }
-        S.items_cap = cap;
+    const size_t off = items_offset(njobs), bytes = off + sizeof(fg_item) * (size_t)nitems;
+    if (bytes > S.cap) {
+        // the slot is idle, so its old buffers are no longer read by the device
+        const size_t cap = std::max(bytes, items_offset(FAST_MAX_JOBS) + sizeof(fg_item) * 65536);
+        uint8_t *host = nullptr, *dev = nullptr;
+        hipError_t e = hipHostMalloc((void **)&host, cap, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc job table");
+        e = hipMalloc((void **)&dev, cap);
+        if (e != hipSuccess) {
+            (void)hipHostFree(host);
+            return hip_fail(c, e, "hipMalloc job table");
+        }
+        memcpy(host, S.host, off);
+        (void)hipHostFree(S.host);
+        (void)hipFree(S.dev);
+        S.host = host;
+        S.dev = dev;
+        S.cap = cap;
     }
-    fill_items(S.host, njobs, S.items_host);
+    const fg_job *jobs_dev = (const fg_job *)S.dev;
+    const fg_item *items_dev = (const fg_item *)(S.dev + off);
+    fill_items((const fg_job *)S.host, njobs, (fg_item *)(S.host + off));
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync(S.dev, S.host, sizeof(fg_job) * njobs, hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(S.dev, S.host, bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(c, e, "job table upload");
-    e = hipMemcpyAsync(S.items_dev, S.items_host, sizeof(fg_item) * nitems, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(c, e, "item map upload");
-    e = fg_launch_batch(S.dev, S.items_dev, njobs, total, total_upper, max_levels, mw1, mh1, all_single,
+    e = fg_launch_batch(jobs_dev, items_dev, njobs, total, total_upper, max_levels, mw1, mh1, all_single,
                         S.counter, c->launch, s);
     if (e != hipSuccess) return hip_fail(c, e, "batch launch");
     rc = record_ticket(c, s, ticket);
@@ -431,7 +441,12 @@ FG_API int fast_wait(fast_ctx *c, uint64_t ticket, int timeout_ms) {
             auto ms = std::chrono::duration_cast<std::chrono::milliseconds>(std::chrono::steady_clock::now() - t0);
             if (ms.count() >= timeout_ms) return fail(c, FAST_ETIMEDOUT, "wait timed out");
         }
-        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        // poll without sleeping for the first 2 ms (a sleep costs tens of
+        // microseconds of latency), then back off
+        if (std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(2))
+            std::this_thread::yield();
+        else
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
 }
 
