@@ -44,8 +44,15 @@ def _load():
                                          ctypes.c_int, ctypes.POINTER(ctypes.c_uint8)]
         lib.fastref_detect_grid.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                             ctypes.c_int, ctypes.c_void_p]
+        lib.fastref_score_kind_at.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_int]
+        lib.fastref_score_map_kind.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(ctypes.c_uint16)]
+        lib.fastref_detect_grid_kind.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
         for f in (lib.fastref_pyr_build, lib.fastref_arc, lib.fastref_score_at,
-                  lib.fastref_score_map, lib.fastref_nms_mask, lib.fastref_detect_grid):
+                  lib.fastref_score_map, lib.fastref_nms_mask, lib.fastref_detect_grid,
+                  lib.fastref_score_kind_at, lib.fastref_score_map_kind, lib.fastref_detect_grid_kind):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -88,16 +95,23 @@ def arc(mask16: int, n: int) -> bool:
     return bool(_load().fastref_arc(mask16, n))
 
 
-def score_at(img: np.ndarray, width: int, x: int, y: int, t: int, n: int) -> int:
+# Score kinds (Section II-D): whole-circle sum, arc sum, maximum threshold.
+SCORE_SADB, SCORE_SADA, SCORE_MT = 0, 1, 2
+
+
+def score_at(img: np.ndarray, width: int, x: int, y: int, t: int, n: int,
+             kind: int = SCORE_SADB) -> int:
     p = _plane(img, width)
-    return int(_load().fastref_score_at(ctypes.byref(p), x, y, t, n))
+    if kind == SCORE_SADB:
+        return int(_load().fastref_score_at(ctypes.byref(p), x, y, t, n))
+    return int(_load().fastref_score_kind_at(ctypes.byref(p), x, y, t, n, kind))
 
 
-def score_map(img: np.ndarray, width: int, t: int, n: int) -> np.ndarray:
+def score_map(img: np.ndarray, width: int, t: int, n: int, kind: int = SCORE_SADB) -> np.ndarray:
     p = _plane(img, width)
     out = np.zeros((img.shape[0], width), np.uint16)
-    rc = _load().fastref_score_map(ctypes.byref(p), t, n,
-                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)))
+    rc = _load().fastref_score_map_kind(ctypes.byref(p), t, n, kind,
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)))
     if rc != 0:
         raise ValueError(f"fastref_score_map failed ({rc})")
     return out
@@ -119,20 +133,20 @@ def grid_dims(width: int, height: int, cell: int) -> tuple[int, int]:
 
 
 def detect_grid_levels(planes: list[tuple[np.ndarray, int]], t: int, n: int,
-                       cell: int) -> np.ndarray:
+                       cell: int, kind: int = SCORE_SADB) -> np.ndarray:
     """Cell slots for an already-built pyramid [(plane, width)]."""
     levels = len(planes)
     arr = (_Plane * levels)(*[_plane(p, w) for p, w in planes])
     gw, gh = grid_dims(planes[0][1], planes[0][0].shape[0], cell)
     out = np.zeros(gw * gh, FEATURE_DTYPE)
-    rc = _load().fastref_detect_grid(arr, levels, t, n, cell, out.ctypes.data)
+    rc = _load().fastref_detect_grid_kind(arr, levels, t, n, cell, kind, out.ctypes.data)
     if rc != 0:
         raise ValueError(f"fastref_detect_grid failed ({rc})")
     return out
 
 
 def detect_grid(img: np.ndarray, width: int, levels: int, t: int, n: int,
-                cell: int) -> tuple[np.ndarray, list[tuple[np.ndarray, int]]]:
+                cell: int, kind: int = SCORE_SADB) -> tuple[np.ndarray, list[tuple[np.ndarray, int]]]:
     """Build the pyramid, then select one feature per cell.  Returns (slots, planes)."""
     planes = pyr_build(img, width, levels)
-    return detect_grid_levels(planes, t, n, cell), planes
+    return detect_grid_levels(planes, t, n, cell, kind), planes

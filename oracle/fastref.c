@@ -78,8 +78,12 @@ int fastref_arc(uint32_t mask16, int n) {
  * tested (score 0); the score is the whole-circle thresholded sum of the
  * winning side, max(sum_bright (p - c - t), sum_dark (c - p - t)), and 0 when
  * the test fails (the paper: "The corner score is 0 if the segment test fails"). */
+static int outside_test_area(const fastref_plane *img, int x, int y) {
+    return x < 3 || y < 3 || x > img->width - 4 || y > img->height - 4;
+}
+
 int fastref_score_at(const fastref_plane *img, int x, int y, int t, int n) {
-    if (x < 3 || y < 3 || x > img->width - 4 || y > img->height - 4) return 0;
+    if (outside_test_area(img, x, y)) return 0;
     int c = px(img, x, y);
     uint32_t bright = 0, dark = 0;
     int sum_bright = 0, sum_dark = 0;
@@ -98,12 +102,80 @@ int fastref_score_at(const fastref_plane *img, int x, int y, int t, int n) {
     return sum_bright > sum_dark ? sum_bright : sum_dark;
 }
 
-int fastref_score_map(const fastref_plane *img, int t, int n, uint16_t *score) {
+/* Is circle point i on a continuous arc of at least n points of `mask`?
+ * Direct check: some start s with i in s..s+n-1 (circularly) and all of
+ * s..s+n-1 set. */
+static int on_arc(uint32_t mask16, int n, int i) {
+    for (int s = 0; s < 16; ++s) {
+        int all = 1, covers = 0;
+        for (int j = 0; j < n; ++j) {
+            int q = (s + j) % 16;
+            if (!((mask16 >> q) & 1u)) { all = 0; break; }
+            if (q == i) covers = 1;
+        }
+        if (all && covers) return 1;
+    }
+    return 0;
+}
+
+/* The paper's other corner scores (Section II-D names three: SAD-B over the
+ * whole circle, SAD-A over the contiguous arc, MT the maximum threshold for
+ * which the point is still a corner).
+ * READING, SAD-A: the thresholded sum of fastref_score_at restricted to the
+ *   circle points that lie on a qualifying arc (a run of at least n points of
+ *   one label), max over the two labels; 0 if the segment test fails.
+ * READING, MT: d = the largest value such that some n consecutive circle points
+ *   all differ from the centre by at least d in the same direction
+ *   (brighter: p - c, darker: c - p).  The segment test with threshold t'
+ *   passes exactly when d > t', so the maximum passing threshold is d - 1; the
+ *   score is d (> t, at most 255) so that a corner never scores 0, and 0 if
+ *   the test fails at t. */
+int fastref_score_kind_at(const fastref_plane *img, int x, int y, int t, int n, int kind) {
+    if (kind == FASTREF_SCORE_SADB) return fastref_score_at(img, x, y, t, n);
+    if (outside_test_area(img, x, y)) return 0;
+    int c = px(img, x, y);
+    int v[16];
+    uint32_t bright = 0, dark = 0;
+    for (int i = 0; i < 16; ++i) {
+        v[i] = px(img, x + CIRCLE_DX[i], y + CIRCLE_DY[i]);
+        if (v[i] > c + t) bright |= 1u << i;
+        else if (v[i] < c - t) dark |= 1u << i;
+    }
+    if (!fastref_arc(bright, n) && !fastref_arc(dark, n)) return 0;
+    if (kind == FASTREF_SCORE_SADA) {
+        int arc_bright = 0, arc_dark = 0;
+        for (int i = 0; i < 16; ++i) {
+            if (on_arc(bright, n, i)) arc_bright += v[i] - c - t;
+            if (on_arc(dark, n, i)) arc_dark += c - v[i] - t;
+        }
+        return arc_bright > arc_dark ? arc_bright : arc_dark;
+    }
+    /* MT */
+    int d = -256;
+    for (int s = 0; s < 16; ++s) {
+        int min_b = 256, min_d = 256;
+        for (int j = 0; j < n; ++j) {
+            int q = v[(s + j) % 16];
+            if (q - c < min_b) min_b = q - c;
+            if (c - q < min_d) min_d = c - q;
+        }
+        if (min_b > d) d = min_b;
+        if (min_d > d) d = min_d;
+    }
+    return d > t ? d : 0;
+}
+
+int fastref_score_map_kind(const fastref_plane *img, int t, int n, int kind, uint16_t *score) {
     if (!plane_ok(img) || !score || t < 0 || t > 255 || n < 1 || n > 16) return -1;
+    if (kind < FASTREF_SCORE_SADB || kind > FASTREF_SCORE_MT) return -1;
     for (int y = 0; y < img->height; ++y)
         for (int x = 0; x < img->width; ++x)
-            score[(size_t)y * img->width + x] = (uint16_t)fastref_score_at(img, x, y, t, n);
+            score[(size_t)y * img->width + x] = (uint16_t)fastref_score_kind_at(img, x, y, t, n, kind);
     return 0;
+}
+
+int fastref_score_map(const fastref_plane *img, int t, int n, uint16_t *score) {
+    return fastref_score_map_kind(img, t, n, FASTREF_SCORE_SADB, score);
 }
 
 /* Does candidate (sa, ia) rank above (sb, ib)?  Order: higher score first,
@@ -146,10 +218,11 @@ int fastref_nms_mask(const uint16_t *score, int width, int height, uint8_t *mask
  * READING: cells are cell x cell level-0 pixels, partial cells at the right and
  * bottom edges are kept; ties across levels prefer the smaller level, ties
  * within a level the smaller row-major index; an empty cell gets the sentinel. */
-int fastref_detect_grid(const fastref_plane *pyr, int levels, int t, int n, int cell,
-                        fastref_feature *out) {
+int fastref_detect_grid_kind(const fastref_plane *pyr, int levels, int t, int n, int cell, int kind,
+                             fastref_feature *out) {
     if (!pyr || !out || levels < 1 || levels > 8 || t < 0 || t > 255 || n < 1 || n > 16)
         return -1;
+    if (kind < FASTREF_SCORE_SADB || kind > FASTREF_SCORE_MT) return -1;
     if (cell < 1 || cell % (1 << (levels - 1)) != 0) return -1;
     for (int k = 0; k < levels; ++k) {
         if (!plane_ok(&pyr[k])) return -1;
@@ -173,7 +246,7 @@ int fastref_detect_grid(const fastref_plane *pyr, int levels, int t, int n, int 
         uint16_t *score = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)w * (size_t)h);
         uint8_t *mask = (uint8_t *)malloc((size_t)w * (size_t)h);
         if (!score || !mask) { free(score); free(mask); return -1; }
-        fastref_score_map(img, t, n, score);
+        fastref_score_map_kind(img, t, n, kind, score);
         fastref_nms_mask(score, w, h, mask);
         for (int y = 0; y < h; ++y) {
             for (int x = 0; x < w; ++x) {
@@ -199,4 +272,9 @@ int fastref_detect_grid(const fastref_plane *pyr, int levels, int t, int n, int 
         free(mask);
     }
     return 0;
+}
+
+int fastref_detect_grid(const fastref_plane *pyr, int levels, int t, int n, int cell,
+                        fastref_feature *out) {
+    return fastref_detect_grid_kind(pyr, levels, t, n, cell, FASTREF_SCORE_SADB, out);
 }

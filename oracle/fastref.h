@@ -54,6 +54,18 @@ int fastref_score_at(const fastref_plane *img, int x, int y, int t, int n);
 /* Score map of a whole plane: score[y*width + x], zeros in the border. */
 int fastref_score_map(const fastref_plane *img, int t, int n, uint16_t *score);
 
+/* Corner score kinds (Section II-D names three).  SADB is the score above.
+ * SADA: the same thresholded sums over only the circle points on a continuous
+ * arc of at least n points of one label.  MT: the largest d such that n
+ * consecutive circle points all differ from the centre by at least d in one
+ * direction (the test at threshold t' passes iff d > t'); the score is d, or 0
+ * when the test fails at t. */
+enum { FASTREF_SCORE_SADB = 0, FASTREF_SCORE_SADA = 1, FASTREF_SCORE_MT = 2 };
+
+/* fastref_score_at / fastref_score_map with a score kind; -1 for a bad kind. */
+int fastref_score_kind_at(const fastref_plane *img, int x, int y, int t, int n, int kind);
+int fastref_score_map_kind(const fastref_plane *img, int t, int n, int kind, uint16_t *score);
+
 /* 3x3 non-maxima suppression (Section I-B, n=1) of a width x height score map:
  * mask[y*width+x] = 1 iff score > 0 and the pixel beats all 8 neighbours by
  * (score descending, row-major index ascending). */
@@ -66,6 +78,10 @@ int fastref_nms_mask(const uint16_t *score, int width, int height, uint8_t *mask
  * in the cell, or the empty sentinel. */
 int fastref_detect_grid(const fastref_plane *pyr, int levels, int t, int n, int cell,
                         fastref_feature *out);
+
+/* fastref_detect_grid with a score kind. */
+int fastref_detect_grid_kind(const fastref_plane *pyr, int levels, int t, int n, int cell, int kind,
+                             fastref_feature *out);
 
 #ifdef __cplusplus
 }

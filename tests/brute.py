@@ -11,7 +11,11 @@ unlikely to appear in both:
 * NMS compares each pixel with its 8 shifted neighbours through one integer
   rank that folds the row-major tie-break into the score;
 * cell selection sorts every survivor of every level by
-  (cell, -score, level, index) and keeps the first per cell.
+  (cell, -score, level, index) and keeps the first per cell;
+* the arc score (SAD-A) marks a circle point as on an arc when the maximal
+  circular run through it is at least n long (runs measured forwards and
+  backwards from the point), and the maximum-threshold score (MT) searches the
+  thresholds t' = t..255 with the plain segment test.
 """
 from __future__ import annotations
 
@@ -39,6 +43,29 @@ def longest_circular_run(bits: np.ndarray) -> np.ndarray:
     return np.minimum(best, 16)
 
 
+def run_through(bits: np.ndarray) -> np.ndarray:
+    """bits: (..., 16) bool.  Length of the maximal circular run of True through
+    each position (0 where False, 16 when all are True)."""
+    b = bits.astype(np.int32)
+    fwd = np.zeros_like(b)
+    bwd = np.zeros_like(b)
+    for i in range(16):
+        # run length starting at i going forwards, and ending at i going backwards
+        f = np.zeros(b.shape[:-1], np.int32)
+        alive = np.ones(b.shape[:-1], bool)
+        for j in range(16):
+            alive &= b[..., (i + j) % 16] == 1
+            f += alive
+        fwd[..., i] = f
+        g = np.zeros(b.shape[:-1], np.int32)
+        alive = np.ones(b.shape[:-1], bool)
+        for j in range(16):
+            alive &= b[..., (i - j) % 16] == 1
+            g += alive
+        bwd[..., i] = g
+    return np.where(b == 1, np.minimum(fwd + bwd - 1, 16), 0)
+
+
 def pyramid(img: np.ndarray, levels: int) -> list[np.ndarray]:
     out = [img.astype(np.int64)]
     for _ in range(1, levels):
@@ -49,7 +76,9 @@ def pyramid(img: np.ndarray, levels: int) -> list[np.ndarray]:
     return [p.astype(np.uint8) for p in out]
 
 
-def score_map(img: np.ndarray, t: int, n: int) -> np.ndarray:
+def score_map(img: np.ndarray, t: int, n: int, kind: int = 0) -> np.ndarray:
+    """kind 0: whole-circle sums; 1: sums over the points on an arc of >= n;
+    2: 1 + the largest threshold t' >= t at which the segment test passes."""
     I = img.astype(np.int64)
     h, w = I.shape
     out = np.zeros((h, w), np.int64)
@@ -59,9 +88,22 @@ def score_map(img: np.ndarray, t: int, n: int) -> np.ndarray:
     ring = np.stack([I[3 + dy:h - 3 + dy, 3 + dx:w - 3 + dx] for dx, dy in circle_offsets()],
                     axis=-1)
     diff = ring - c[..., None]
+
+    def passes(tt):
+        return (longest_circular_run(diff > tt) >= n) | (longest_circular_run(diff < -tt) >= n)
+
+    corner = passes(t)
     bright = diff > t
     dark = diff < -t
-    corner = (longest_circular_run(bright) >= n) | (longest_circular_run(dark) >= n)
+    if kind == 2:
+        best = np.full(c.shape, -1, np.int64)
+        for tt in range(t, 256):
+            best = np.where(passes(tt), tt, best)
+        out[3:h - 3, 3:w - 3] = np.where(corner, best + 1, 0)
+        return out
+    if kind == 1:
+        bright = bright & (run_through(bright) >= n)
+        dark = dark & (run_through(dark) >= n)
     sb = np.where(bright, diff - t, 0).sum(-1)
     sd = np.where(dark, -diff - t, 0).sum(-1)
     out[3:h - 3, 3:w - 3] = np.where(corner, np.maximum(sb, sd), 0)
@@ -82,14 +124,14 @@ def nms(score: np.ndarray) -> np.ndarray:
     return keep
 
 
-def detect_grid(img: np.ndarray, levels: int, t: int, n: int, cell: int):
+def detect_grid(img: np.ndarray, levels: int, t: int, n: int, cell: int, kind: int = 0):
     """img: (H, W) uint8 without padding.  Returns (slots list of tuples, planes)."""
     planes = pyramid(img, levels)
     H, W = img.shape
     gw, gh = -(-W // cell), -(-H // cell)
     cands = []
     for k, P in enumerate(planes):
-        s = score_map(P, t, n)
+        s = score_map(P, t, n, kind)
         keep = nms(s)
         ys, xs = np.nonzero(keep)
         for y, x in zip(ys.tolist(), xs.tolist()):

@@ -116,6 +116,26 @@ def test_launch_shapes_agree(ctx):
         ctx.set_launch(64, 256, 3)
 
 
+def test_set_launch_rejects_bad_shapes(ctx):
+    """Blocks must be multiples of 64 in 64..512, regions 16..256, 1..16
+    workgroups per CU; a rejected shape leaves the previous one in force."""
+    try:
+        for region, block, bpc in ((64, 100, 3), (64, 0, 3), (64, 576, 3), (8, 256, 3), (300, 256, 3),
+                                   (64, 256, 0), (64, 256, 17)):
+            with pytest.raises(fastgrid.FastError) as ei:
+                ctx.set_launch(region, block, bpc)
+            assert ei.value.code == fastgrid.FAST_EINVAL
+        for block in (192, 320, 448):
+            ctx.set_launch(64, block, 2)
+    finally:
+        ctx.set_launch(64, 256, 3)
+    spec = synth.PLAIN_320
+    img = spec.make()
+    want, _ = oracle.detect_grid(img, spec.width, spec.levels, spec.t, spec.n, spec.cell)
+    got, _ = run_plain(ctx, img, spec.width, spec.levels, spec.t, spec.n, spec.cell)
+    assert np.array_equal(got, want)
+
+
 def test_pyr_build_entry_point(ctx):
     img = synth.frame(333, 222, seed=77, nshapes=20, sigma=5, pad_garbage=True)
     pyr = fastgrid.Pyramid(333, 222, 5)

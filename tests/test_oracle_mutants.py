@@ -27,6 +27,10 @@ MUTANTS = {
     "no_level_scale_up": ("long cx = ((long)x << k) / cell", "long cx = (long)x / cell"),
     "nms_skips_diagonals": ("if (dx == 0 && dy == 0) continue;",
                             "if (dx == 0 || dy == 0) { if (dx == 0 && dy == 0) continue; } else continue;"),
+    "arc_sum_counts_off_arc": ("if (on_arc(bright, n, i)) arc_bright", "if ((bright >> i) & 1u) arc_bright"),
+    "arc_sum_drops_dark": ("return arc_bright > arc_dark ? arc_bright : arc_dark;", "return arc_bright;"),
+    "max_threshold_off_by_one": ("return d > t ? d : 0;", "return d > t ? d - 1 : 0;"),
+    "max_threshold_short_window": ("            int q = v[(s + j) % 16];", "            if (j == n - 1) break;\n            int q = v[(s + j) % 16];"),
 }
 
 

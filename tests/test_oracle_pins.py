@@ -419,6 +419,107 @@ def test_brute_force_score_and_nms_maps():
         assert np.array_equal(oracle.nms_mask(s).astype(bool), brute.nms(s))
 
 
+# ---------------------------------------------------------------- score kinds
+
+def circle_points():
+    """Circle offsets in cyclic order, derived independently of the oracle."""
+    return brute.circle_offsets()
+
+
+def test_arc_score_and_max_threshold_hand_values():
+    """An arc of 9 bright points (values 150..158 around a centre of 100) plus one
+    isolated bright point (200) off the arc, t = 10, N = 9: the whole-circle
+    sum counts the isolated point, the arc sum does not, and the maximum
+    threshold is set by the arc's weakest point."""
+    img = const_img(9, 9, 100)
+    pts = circle_points()
+    for j in range(9):
+        dx, dy = pts[j]
+        img[4 + dy, 4 + dx] = 150 + j
+    dx, dy = pts[12]
+    img[4 + dy, 4 + dx] = 200
+    arc = sum(150 + j - 100 - 10 for j in range(9))            # 9 * 44 = 396
+    assert oracle.score_at(img, 9, 4, 4, 10, 9, oracle.SCORE_SADB) == arc + (200 - 100 - 10)
+    assert oracle.score_at(img, 9, 4, 4, 10, 9, oracle.SCORE_SADA) == arc
+    assert oracle.score_at(img, 9, 4, 4, 10, 9, oracle.SCORE_MT) == 150 - 100
+    # just above the arc's weakest difference the test fails at every kind
+    for kind in (oracle.SCORE_SADB, oracle.SCORE_SADA, oracle.SCORE_MT):
+        assert oracle.score_at(img, 9, 4, 4, 50, 9, kind) == 0
+        assert oracle.score_at(img, 9, 4, 4, 49, 9, kind) > 0
+
+
+def test_arc_score_two_runs_and_dark_side():
+    """N = 5: two bright runs of 5 both count for the arc sum; a dark run of 6
+    wins when its sum is larger."""
+    pts = circle_points()
+    img = const_img(9, 9, 120)
+    for j in (0, 1, 2, 3, 4, 8, 9, 10, 11, 12):
+        dx, dy = pts[j]
+        img[4 + dy, 4 + dx] = 140          # bright by 20 > t = 5
+    sada = oracle.score_at(img, 9, 4, 4, 5, 5, oracle.SCORE_SADA)
+    assert sada == 10 * (140 - 120 - 5)
+    img2 = const_img(9, 9, 120)
+    for j in range(6):
+        dx, dy = pts[j]
+        img2[4 + dy, 4 + dx] = 60          # dark by 60
+    for j in (8, 9, 10, 11, 12):
+        dx, dy = pts[j]
+        img2[4 + dy, 4 + dx] = 130         # bright by 10
+    assert oracle.score_at(img2, 9, 4, 4, 5, 5, oracle.SCORE_SADA) == 6 * (120 - 60 - 5)
+    assert oracle.score_at(img2, 9, 4, 4, 5, 5, oracle.SCORE_MT) == 60
+
+
+def test_max_threshold_is_the_segment_test_boundary():
+    """The defining property: with threshold t' the whole-circle score is nonzero
+    exactly when t' is below the max-threshold score taken at t = 0."""
+    rng = np.random.default_rng(2024)
+    for trial in range(150):
+        img = rng.integers(0, 256, size=(7, 7)).astype(np.uint8)
+        if trial % 3 == 0:
+            img = (img // 64 * 64).astype(np.uint8)
+        n = int(rng.integers(1, 17))
+        d0 = oracle.score_at(img, 7, 3, 3, 0, n, oracle.SCORE_MT)
+        for tt in range(0, 256, 3):
+            passes = oracle.score_at(img, 7, 3, 3, tt, n, oracle.SCORE_SADB) > 0
+            assert passes == (d0 > tt), (trial, n, tt, d0)
+            mt = oracle.score_at(img, 7, 3, 3, tt, n, oracle.SCORE_MT)
+            assert mt == (d0 if d0 > tt else 0)
+
+
+def test_score_kind_relations_on_synthetic_frames():
+    """All kinds share the segment test, so the same pixels score nonzero; the
+    arc sum never exceeds the whole-circle sum; MT lies in (t, 255]."""
+    from paper_2003_13493_amd import synth
+    img = synth.frame(96, 80, seed=11, nshapes=25, sigma=4)
+    for t, n in ((10, 9), (20, 12), (5, 3)):
+        b = oracle.score_map(img, 96, t, n, oracle.SCORE_SADB)
+        a = oracle.score_map(img, 96, t, n, oracle.SCORE_SADA)
+        m = oracle.score_map(img, 96, t, n, oracle.SCORE_MT)
+        assert np.array_equal(b > 0, a > 0) and np.array_equal(b > 0, m > 0)
+        assert np.all(a <= b)
+        assert np.all((m == 0) | ((m > t) & (m <= 255)))
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_score_kinds_brute_force_tiny_images(kind):
+    rng = np.random.default_rng(99 + kind)
+    for trial in range(120):
+        h, w = int(rng.integers(8, 30)), int(rng.integers(8, 30))
+        levels = int(rng.integers(1, 3))
+        alphabet = rng.choice([3, 5, 256])
+        vals = np.sort(rng.choice(256, size=alphabet, replace=False)) if alphabet < 256 \
+            else np.arange(256)
+        img = vals[rng.integers(0, len(vals), size=(h, w))].astype(np.uint8)
+        t = int(rng.choice([0, 1, 5, 10, 30]))
+        n = int(rng.integers(1, 17))
+        cell = (1 << (levels - 1)) * int(rng.integers(1, 4))
+        s = oracle.score_map(padded(img), w, t, n, kind)
+        assert np.array_equal(s, brute.score_map(img, t, n, kind)), (trial, t, n)
+        got, _ = oracle.detect_grid(padded(img), w, levels, t, n, cell, kind)
+        want, _ = brute.detect_grid(img, levels, t, n, cell, kind)
+        assert as_tuples(got) == want, (trial, h, w, levels, t, n, cell)
+
+
 def test_invalid_arguments_rejected():
     img = const_img(16, 16, 9)
     with pytest.raises(ValueError):
