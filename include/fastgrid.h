@@ -86,6 +86,22 @@ typedef struct {
     uint8_t reserved;
 } fast_feature;
 
+/* Corner score kinds (Section II-D names three; "the corner score is 0 if the
+ * segment test fails" holds for each):
+ *   FAST_SCORE_SADB  max(sum over brighter circle points of (p-c-t),
+ *                        sum over darker circle points of (c-p-t)), the default;
+ *   FAST_SCORE_SADA  the same two sums over only the circle points that lie on
+ *                    a continuous arc of at least n points of their label;
+ *   FAST_SCORE_MT    the largest d such that n consecutive circle points all
+ *                    exceed the centre by at least d, or all fall below it by
+ *                    at least d.  The segment test with threshold t' passes
+ *                    exactly when d > t', so the maximum passing threshold is
+ *                    d - 1; the score is d (t < d <= 255).
+ * NMS and the cell arg-max compare scores of the chosen kind. */
+#define FAST_SCORE_SADB 0
+#define FAST_SCORE_SADA 1
+#define FAST_SCORE_MT 2
+
 /* One detection request for the batched entry point. */
 typedef struct {
     const fast_plane *pyr;   /* host array of `levels` planes: [0] input, [1..] written */
@@ -94,6 +110,7 @@ typedef struct {
     int32_t n;               /* arc length N, 1..16 */
     int32_t cell;            /* cell side in level-0 pixels, multiple of 2^(levels-1), <= 256 */
     fast_feature *out;       /* device array of gw*gh slots, row-major */
+    int32_t score;           /* FAST_SCORE_*; 0 (zero-initialised jobs) is FAST_SCORE_SADB */
 } fast_job;
 
 /* Create a context on HIP device `hip_device`.  *out receives the context.
@@ -132,6 +149,12 @@ int fast_pyr_build(fast_ctx *ctx, const fast_plane *pyr, int levels, void *strea
  * FAST_EHIP if a launch fails. */
 int fast_detect_grid(fast_ctx *ctx, const fast_plane *pyr, int levels, int t, int n,
                      int cell, fast_feature *out, void *stream);
+
+/* fast_detect_grid with a corner score kind (FAST_SCORE_*; Section II-D).
+ * fast_detect_grid is this call with FAST_SCORE_SADB.
+ * Errors: as fast_detect_grid, and FAST_EINVAL for an unknown score kind. */
+int fast_detect_grid_score(fast_ctx *ctx, const fast_plane *pyr, int levels, int t, int n,
+                           int cell, int score, fast_feature *out, void *stream);
 
 /* Batched path: all `njobs` requests (1..FAST_MAX_JOBS, any mix of sizes and
  * parameters) run in one persistent launch fed by a device-side work queue.

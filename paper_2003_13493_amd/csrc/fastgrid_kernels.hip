@@ -32,6 +32,8 @@
 // P1-P4 need no workgroup barrier.  Both filters are necessary conditions of
 // the segment test, so a pixel they reject has score 0; the cascade never
 // changes a result.
+#include <type_traits>
+
 #include "fg_internal.h"
 
 namespace {
@@ -187,24 +189,104 @@ __device__ __forceinline__ s16x2 compass(s16x2 C, s16x2 N, s16x2 E, s16x2 S, s16
 constexpr int CDX[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
 constexpr int CDY[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
 
-// Full segment test and score (Eq. (1)) of the pixel at p.  The sums
+// Bits i .. i+n-1 (circularly, 0 <= i < 16) set for every bit i of `starts`
+// (a 16-bit mask): the circle points covered by the arcs starting there.
+__device__ __forceinline__ uint32_t arc_cover(uint32_t starts, int n) {
+    uint32_t c = starts;
+    int have = 1;
+    while (have * 2 <= n) {
+        c |= c << have;
+        have *= 2;
+    }
+    if (have < n) c |= c << (n - have);
+    return (c | (c >> 16)) & 0xFFFFu;
+}
+
+// w[i] <- min(w[i], w[(i + k) & 15]) for both 16-bit halves.
+template <int K>
+__device__ __forceinline__ void window_step(s16x2 (&w)[16]) {
+    s16x2 u[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) u[i] = vmin(w[i], w[(i + K) & 15]);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) w[i] = u[i];
+}
+
+template <int K>
+__device__ __forceinline__ void rotate(s16x2 (&w)[16]) {
+    s16x2 u[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) u[i] = w[(i + K) & 15];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) w[i] = u[i];
+}
+
+// Maximum-threshold score from the 16 circle values: the largest d such that
+// n consecutive points all exceed the centre by at least d (low half: v - c)
+// or fall below it by at least d (high half: c - v).  Window minima by
+// doubling (uniform steps), the remainder by a barrel rotation, so every
+// register index is static.
+__device__ __forceinline__ int max_threshold(const uint32_t (&v)[16], uint32_t cv, int n) {
+    s16x2 w[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) w[i] = s16x2{(short)((int)v[i] - (int)cv), (short)((int)cv - (int)v[i])};
+    int have = 1;
+    if (n >= 2) { window_step<1>(w); have = 2; }
+    if (n >= 4) { window_step<2>(w); have = 4; }
+    if (n >= 8) { window_step<4>(w); have = 8; }
+    if (n >= 16) { window_step<8>(w); have = 16; }
+    const int r = n - have;   // 0 <= r < have
+    if (r) {
+        s16x2 u[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) u[i] = w[i];
+        if (r & 1) rotate<1>(u);
+        if (r & 2) rotate<2>(u);
+        if (r & 4) rotate<4>(u);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) w[i] = vmin(w[i], u[i]);
+    }
+    s16x2 m = w[0];
+#pragma unroll
+    for (int i = 1; i < 16; ++i) m = vmax(m, w[i]);
+    return m.x > m.y ? m.x : m.y;
+}
+
+// Corner score kinds (Section II-D): FAST_SCORE_SADB sums over the whole
+// circle, FAST_SCORE_SADA over the points on a qualifying arc, FAST_SCORE_MT
+// is the maximum threshold at which the test still passes (plus one).
+// Segment test and score of the pixel at p; 0 if the test fails.  The sums
 // accumulate max(v - (c+t), 0) and max((c-t) - v, 0), each one saturating
 // unsigned subtraction.
+template <int KIND>
 __device__ __forceinline__ uint32_t full_score(const uint8_t *p, int t, int n) {
     const uint32_t cv = p[0];
     const uint32_t hi = cv + (uint32_t)t;
     const uint32_t lo = (int)cv - t > 0 ? cv - (uint32_t)t : 0u;   // darker needs v < c-t; none if c-t <= 0
+    uint32_t v[16];
     uint32_t bm = 0, dm = 0, sb = 0, sd = 0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        const uint32_t v = p[CIRC(j)];
-        bm = __builtin_amdgcn_alignbit(bm, hi - v, 31);   // sign: v > c+t
-        dm = __builtin_amdgcn_alignbit(dm, v - lo, 31);   // sign: v < c-t
-        sb += __builtin_elementwise_sub_sat(v, hi);
-        sd += __builtin_elementwise_sub_sat(lo, v);
+        v[j] = p[CIRC(j)];
+        bm = __builtin_amdgcn_alignbit(bm, hi - v[j], 31);   // sign: v > c+t; point j at bit 15-j
+        dm = __builtin_amdgcn_alignbit(dm, v[j] - lo, 31);   // sign: v < c-t
+        if constexpr (KIND == FAST_SCORE_SADB) {
+            sb += __builtin_elementwise_sub_sat(v[j], hi);
+            sd += __builtin_elementwise_sub_sat(lo, v[j]);
+        }
     }
     const uint32_t b2 = bm | (bm << 16), d2 = dm | (dm << 16);
-    if (((runs(b2, n) | runs(d2, n)) & 0xFFFFu) == 0) return 0;
+    const uint32_t rb = runs(b2, n) & 0xFFFFu, rd = runs(d2, n) & 0xFFFFu;
+    if ((rb | rd) == 0) return 0;
+    if constexpr (KIND == FAST_SCORE_MT) return (uint32_t)max_threshold(v, cv, n);
+    if constexpr (KIND == FAST_SCORE_SADA) {
+        const uint32_t cb = arc_cover(rb, n), cd = arc_cover(rd, n);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            sb += __builtin_elementwise_sub_sat(v[j], hi) & (0u - ((cb >> (15 - j)) & 1u));
+            sd += __builtin_elementwise_sub_sat(lo, v[j]) & (0u - ((cd >> (15 - j)) & 1u));
+        }
+    }
     return sb > sd ? sb : sd;
 }
 
@@ -221,6 +303,7 @@ struct Geo {
 
 struct Params {
     int t, n, kc, k8;    // threshold, arc length, floor(N/4), floor(N/2)
+    int kind;            // corner score kind (FAST_SCORE_*)
     int cell;            // level-0 cell side
     int rx0, ry0;        // region origin in level-0 pixels
     int ncx;             // cells across the region
@@ -575,17 +658,25 @@ __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Ge
     const LevelMap m2 = level_map(g2, 96, T2 - 96 * LP, g2.sy, g2.ey, P);
     uint16_t *maps = (uint16_t *)smem;
     const int lane = lane_id();
-    // P4: full segment test and score into the level's score map
-    for (int i = lane; i < n2; i += 64) {
-        const uint16_t e = list[i];
-        const uint32_t s = full_score(smem + (e & 0x3FFF), P.t, P.n);
-        if (s) {
-            const int l = e >> 14;
-            int row, col;
-            tile_rc(e & 0x3FFF, row, col);
-            maps[row * sel3(l, m0.mp, m1.mp, m2.mp) + col + sel3(l, m0.mbias, m1.mbias, m2.mbias)] =
-                (uint16_t)s;
+    // P4: full segment test and score into the level's score map (one loop
+    // per score kind, so each compiles to straight-line code)
+    auto score_pass = [&](auto kind) {
+        for (int i = lane; i < n2; i += 64) {
+            const uint16_t e = list[i];
+            const uint32_t s = full_score<decltype(kind)::value>(smem + (e & 0x3FFF), P.t, P.n);
+            if (s) {
+                const int l = e >> 14;
+                int row, col;
+                tile_rc(e & 0x3FFF, row, col);
+                maps[row * sel3(l, m0.mp, m1.mp, m2.mp) + col + sel3(l, m0.mbias, m1.mbias, m2.mbias)] =
+                    (uint16_t)s;
+            }
         }
+    };
+    switch (P.kind) {
+        case FAST_SCORE_SADA: score_pass(std::integral_constant<int, FAST_SCORE_SADA>()); break;
+        case FAST_SCORE_MT: score_pass(std::integral_constant<int, FAST_SCORE_MT>()); break;
+        default: score_pass(std::integral_constant<int, FAST_SCORE_SADB>()); break;
     }
     before();
     __syncthreads();   // every level's scores, ring included, are in the maps
@@ -878,6 +969,7 @@ __device__ __forceinline__ Region region_of(const fg_job &J, int region) {
     R.ncy = min(J.rcells, J.gh - R.ryi * J.rcells);
     R.P.t = J.t;
     R.P.n = J.n;
+    R.P.kind = J.score;
     R.P.kc = J.n >> 2;
     R.P.k8 = J.n >> 1;
     R.P.cell = J.cell;

@@ -16,7 +16,7 @@
 
 static_assert(sizeof(fast_plane) == 24, "fast_plane layout is part of the ABI");
 static_assert(sizeof(fast_feature) == 8, "fast_feature layout is part of the ABI");
-static_assert(sizeof(fast_job) == 32, "fast_job layout is part of the ABI");
+static_assert(sizeof(fast_job) == 40, "fast_job layout is part of the ABI");
 
 namespace {
 
@@ -117,12 +117,13 @@ int check_params(fast_ctx *c, int levels, int t, int n, int cell) {
     return FAST_OK;
 }
 
-int make_job(fast_ctx *c, const fast_plane *pyr, int levels, int t, int n, int cell, fast_feature *out,
-             fg_job &j) {
+int make_job(fast_ctx *c, const fast_plane *pyr, int levels, int t, int n, int cell, int score,
+             fast_feature *out, fg_job &j) {
     int rc = check_pyr(c, pyr, levels);
     if (rc) return rc;
     rc = check_params(c, levels, t, n, cell);
     if (rc) return rc;
+    if (score < FAST_SCORE_SADB || score > FAST_SCORE_MT) return fail(c, FAST_EINVAL, "unknown score kind");
     if (!out) return fail(c, FAST_EINVAL, "out is NULL");
     memset(&j, 0, sizeof(j));
     for (int k = 0; k < levels; ++k) {
@@ -135,6 +136,7 @@ int make_job(fast_ctx *c, const fast_plane *pyr, int levels, int t, int n, int c
     j.t = t;
     j.n = n;
     j.cell = cell;
+    j.score = score;
     j.out = out;
     fg_job_layout(j, c->launch);
     return FAST_OK;
@@ -180,7 +182,7 @@ int build_table(fast_ctx *c, const fast_job *jobs, int njobs, fg_job *table, int
     max_h1 = 1;
     for (int i = 0; i < njobs; ++i) {
         const fast_job &q = jobs[i];
-        int rc = make_job(c, q.pyr, q.levels, q.t, q.n, q.cell, q.out, table[i]);
+        int rc = make_job(c, q.pyr, q.levels, q.t, q.n, q.cell, q.score, q.out, table[i]);
         if (rc) {
             c->err = "job " + std::to_string(i) + ": " + c->err;
             return rc;
@@ -344,9 +346,14 @@ FG_API int fast_pyr_build(fast_ctx *c, const fast_plane *pyr, int levels, void *
 
 FG_API int fast_detect_grid(fast_ctx *c, const fast_plane *pyr, int levels, int t, int n, int cell,
                             fast_feature *out, void *stream) {
+    return fast_detect_grid_score(c, pyr, levels, t, n, cell, FAST_SCORE_SADB, out, stream);
+}
+
+FG_API int fast_detect_grid_score(fast_ctx *c, const fast_plane *pyr, int levels, int t, int n, int cell,
+                                  int score, fast_feature *out, void *stream) {
     if (!c) return FAST_EINVAL;
     fg_job j;
-    int rc = make_job(c, pyr, levels, t, n, cell, out, j);
+    int rc = make_job(c, pyr, levels, t, n, cell, score, out, j);
     if (rc) return rc;
     DeviceGuard g(c->device);
     hipError_t e = fg_launch_plain(j, c->launch, (hipStream_t)stream);

@@ -14,6 +14,7 @@ struct fg_job {
     int32_t h[FAST_MAX_LEVELS];
     int32_t pitch[FAST_MAX_LEVELS];
     int32_t levels, t, n, cell;
+    int32_t score;                   // corner score kind (FAST_SCORE_*)
     fast_feature *out;               // gw*gh slots
     int32_t gw, gh;                  // grid size in cells
     int32_t rcells;                  // cells per region side

@@ -26,8 +26,12 @@ FEATURE_DTYPE = np.dtype([("x", "<u2"), ("y", "<u2"), ("score", "<u2"),
                           ("level", "u1"), ("reserved", "u1")])
 EMPTY = (0xFFFF, 0xFFFF, 0, 0xFF)
 
+# Corner score kinds (fast_job.score, fast_detect_grid_score).
+FAST_SCORE_SADB, FAST_SCORE_SADA, FAST_SCORE_MT = 0, 1, 2
+
 EXPORTS = ("fast_ctx_create", "fast_ctx_destroy", "fast_strerror", "fast_last_error",
            "fast_pyr_dims", "fast_grid_dims", "fast_pyr_build", "fast_detect_grid",
+           "fast_detect_grid_score",
            "fast_submit", "fast_poll", "fast_wait", "fast_plan_create", "fast_plan_launch",
            "fast_plan_destroy", "fast_set_launch")
 
@@ -40,7 +44,7 @@ class fast_plane(ctypes.Structure):
 class fast_job(ctypes.Structure):
     _fields_ = [("pyr", ctypes.POINTER(fast_plane)), ("levels", ctypes.c_int32),
                 ("t", ctypes.c_int32), ("n", ctypes.c_int32), ("cell", ctypes.c_int32),
-                ("out", ctypes.c_void_p)]
+                ("out", ctypes.c_void_p), ("score", ctypes.c_int32)]
 
 
 class FastError(RuntimeError):
@@ -74,6 +78,7 @@ def load() -> ctypes.CDLL:
             "fast_grid_dims": ([i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
             "fast_pyr_build": ([vp, P, i32, vp], i32),
             "fast_detect_grid": ([vp, P, i32, i32, i32, i32, vp, vp], i32),
+            "fast_detect_grid_score": ([vp, P, i32, i32, i32, i32, i32, vp, vp], i32),
             "fast_submit": ([vp, ctypes.POINTER(fast_job), i32, vp, u64p], i32),
             "fast_poll": ([vp, ctypes.c_uint64], i32),
             "fast_wait": ([vp, ctypes.c_uint64, i32], i32),
@@ -135,6 +140,12 @@ def fast_detect_grid(ctx, planes, levels: int, t: int, n: int, cell: int, out_pt
                      stream=None) -> None:
     _check(ctx, load().fast_detect_grid(ctx, planes, levels, t, n, cell, out_ptr,
                                         _stream(stream)), "fast_detect_grid")
+
+
+def fast_detect_grid_score(ctx, planes, levels: int, t: int, n: int, cell: int, score: int,
+                           out_ptr: int, stream=None) -> None:
+    _check(ctx, load().fast_detect_grid_score(ctx, planes, levels, t, n, cell, score, out_ptr,
+                                              _stream(stream)), "fast_detect_grid_score")
 
 
 def fast_submit(ctx, jobs, njobs: int, stream=None) -> int:
@@ -260,17 +271,24 @@ class Context:
     def pyr_build(self, pyr: Pyramid, stream=None) -> None:
         fast_pyr_build(self.handle, pyr.planes, pyr.levels, stream)
 
-    def detect(self, pyr: Pyramid, t: int, n: int, cell: int, grid: Grid, stream=None) -> None:
-        fast_detect_grid(self.handle, pyr.planes, pyr.levels, t, n, cell, grid.ptr, stream)
+    def detect(self, pyr: Pyramid, t: int, n: int, cell: int, grid: Grid, stream=None,
+               score: int = FAST_SCORE_SADB) -> None:
+        if score == FAST_SCORE_SADB:
+            fast_detect_grid(self.handle, pyr.planes, pyr.levels, t, n, cell, grid.ptr, stream)
+        else:
+            fast_detect_grid_score(self.handle, pyr.planes, pyr.levels, t, n, cell, score, grid.ptr,
+                                   stream)
 
     @staticmethod
     def make_jobs(items) -> ctypes.Array:
-        """items: iterable of (Pyramid, t, n, cell, Grid)."""
+        """items: iterable of (Pyramid, t, n, cell, Grid) or (Pyramid, t, n, cell, Grid, score)."""
         items = list(items)
         arr = (fast_job * len(items))()
-        for i, (pyr, t, n, cell, grid) in enumerate(items):
+        for i, it in enumerate(items):
+            pyr, t, n, cell, grid = it[:5]
+            score = it[5] if len(it) > 5 else FAST_SCORE_SADB
             arr[i] = fast_job(ctypes.cast(pyr.planes, ctypes.POINTER(fast_plane)), pyr.levels,
-                              t, n, cell, grid.ptr)
+                              t, n, cell, grid.ptr, score)
         return arr
 
     def submit(self, jobs: ctypes.Array, stream=None) -> int:

@@ -39,7 +39,7 @@ def test_library_exports_nothing_else():
 def test_struct_layouts():
     assert ctypes.sizeof(fastgrid.fast_plane) == 24
     assert fastgrid.FEATURE_DTYPE.itemsize == 8
-    assert ctypes.sizeof(fastgrid.fast_job) == 32
+    assert ctypes.sizeof(fastgrid.fast_job) == 40
 
 
 def test_pyr_and_grid_dims():
