@@ -326,6 +326,27 @@ def main() -> int:
         ctx.plan_destroy(g)
 
     log(f"batched: {ms_per_step:.4f} ms/step")
+    # ---- the same batch with the paper's other corner scores (Section II-D):
+    # each kind gets its own resident plans over the same frames and outputs
+    kinds_ms = {"sadb": round(ms_per_step, 5)}
+    for name, kind in (("sada", fastgrid.FAST_SCORE_SADA), ("mt", fastgrid.FAST_SCORE_MT)):
+        kplans = []
+        for inst in insts:
+            kjobs = fastgrid.Context.make_jobs(
+                (p, s.t, s.n, s.cell, g, kind) for p, s, g in zip(inst[1], inst[0], inst[2]))
+            kplans.append(ctx.plan_create(kjobs))
+        for i in range(args.warmup):
+            ctx.plan_launch(kplans[i % len(kplans)], stream, ticket=False)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(args.steps):
+            ctx.plan_launch(kplans[i % len(kplans)], stream, ticket=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        kinds_ms[name] = round(e0.elapsed_time(e1) / args.steps, 5)
+        for k in kplans:
+            ctx.plan_destroy(k)
+    log(f"score kinds, ms/step: {kinds_ms}")
     # ---- plain path over the same 64 frames: one launch per frame
     specs, pyrs, grids = insts[0][0], insts[0][1], insts[0][2]
     for _ in range(3):
@@ -386,6 +407,8 @@ def main() -> int:
             "algorithmic_bytes_per_launch": bytes_per_step,
         },
         "graph_replay_ms_per_step": round(graph_ms, 5),
+        "score_kinds_ms_per_step": {"workload": "the same batch with every job scored as SAD-B (the "
+                                                "headline), SAD-A or MT", **kinds_ms},
         "step_ms_p50": round(float(np.percentile(step_ms, 50)), 5),
         "step_ms_p99": round(float(np.percentile(step_ms, 99)), 5),
         "plain": {
