@@ -50,9 +50,14 @@ def _load():
                                                ctypes.POINTER(ctypes.c_uint16)]
         lib.fastref_detect_grid_kind.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                  ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        lib.fastref_nms_mask_radius.argtypes = [ctypes.POINTER(ctypes.c_uint16), ctypes.c_int,
+                                                ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8)]
+        lib.fastref_detect_grid_nms.argtypes = [pp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
         for f in (lib.fastref_pyr_build, lib.fastref_arc, lib.fastref_score_at,
                   lib.fastref_score_map, lib.fastref_nms_mask, lib.fastref_detect_grid,
-                  lib.fastref_score_kind_at, lib.fastref_score_map_kind, lib.fastref_detect_grid_kind):
+                  lib.fastref_score_kind_at, lib.fastref_score_map_kind, lib.fastref_detect_grid_kind,
+                  lib.fastref_nms_mask_radius, lib.fastref_detect_grid_nms):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -117,12 +122,12 @@ def score_map(img: np.ndarray, width: int, t: int, n: int, kind: int = SCORE_SAD
     return out
 
 
-def nms_mask(score: np.ndarray) -> np.ndarray:
+def nms_mask(score: np.ndarray, radius: int = 1) -> np.ndarray:
     s = np.ascontiguousarray(score, dtype=np.uint16)
     h, w = s.shape
     out = np.zeros((h, w), np.uint8)
-    rc = _load().fastref_nms_mask(s.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)), w, h,
-                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    rc = _load().fastref_nms_mask_radius(s.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)), w, h,
+                                         radius, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
     if rc != 0:
         raise ValueError(f"fastref_nms_mask failed ({rc})")
     return out
@@ -133,20 +138,21 @@ def grid_dims(width: int, height: int, cell: int) -> tuple[int, int]:
 
 
 def detect_grid_levels(planes: list[tuple[np.ndarray, int]], t: int, n: int,
-                       cell: int, kind: int = SCORE_SADB) -> np.ndarray:
+                       cell: int, kind: int = SCORE_SADB, radius: int = 1) -> np.ndarray:
     """Cell slots for an already-built pyramid [(plane, width)]."""
     levels = len(planes)
     arr = (_Plane * levels)(*[_plane(p, w) for p, w in planes])
     gw, gh = grid_dims(planes[0][1], planes[0][0].shape[0], cell)
     out = np.zeros(gw * gh, FEATURE_DTYPE)
-    rc = _load().fastref_detect_grid_kind(arr, levels, t, n, cell, kind, out.ctypes.data)
+    rc = _load().fastref_detect_grid_nms(arr, levels, t, n, cell, kind, radius, out.ctypes.data)
     if rc != 0:
         raise ValueError(f"fastref_detect_grid failed ({rc})")
     return out
 
 
 def detect_grid(img: np.ndarray, width: int, levels: int, t: int, n: int,
-                cell: int, kind: int = SCORE_SADB) -> tuple[np.ndarray, list[tuple[np.ndarray, int]]]:
+                cell: int, kind: int = SCORE_SADB,
+                radius: int = 1) -> tuple[np.ndarray, list[tuple[np.ndarray, int]]]:
     """Build the pyramid, then select one feature per cell.  Returns (slots, planes)."""
     planes = pyr_build(img, width, levels)
-    return detect_grid_levels(planes, t, n, cell, kind), planes
+    return detect_grid_levels(planes, t, n, cell, kind, radius), planes

@@ -186,18 +186,19 @@ static int ranks_above(int sa, long ia, int sb, long ib) {
     return ia < ib;
 }
 
-/* 3x3 non-maxima suppression (Section I-B: the Moore neighbourhood of side
- * 2n+1, here n=1; Section II-C: each thread checks that its response is the
- * maximum of its neighbourhood).  Neighbours outside the map count as score 0. */
-int fastref_nms_mask(const uint16_t *score, int width, int height, uint8_t *mask) {
-    if (!score || !mask || width < 1 || height < 1) return -1;
+/* Non-maxima suppression over the Moore neighbourhood of side 2r+1 (Section
+ * I-B, where the paper calls the radius n; Section II-C: each thread checks
+ * that its response is the maximum of its neighbourhood).  Neighbours outside
+ * the map count as score 0. */
+int fastref_nms_mask_radius(const uint16_t *score, int width, int height, int r, uint8_t *mask) {
+    if (!score || !mask || width < 1 || height < 1 || r < 1 || r > 4) return -1;
     for (int y = 0; y < height; ++y) {
         for (int x = 0; x < width; ++x) {
             long idx = (long)y * width + x;
             int s = score[idx];
             int keep = s > 0;
-            for (int dy = -1; dy <= 1 && keep; ++dy) {
-                for (int dx = -1; dx <= 1 && keep; ++dx) {
+            for (int dy = -r; dy <= r && keep; ++dy) {
+                for (int dx = -r; dx <= r && keep; ++dx) {
                     if (dx == 0 && dy == 0) continue;
                     int qx = x + dx, qy = y + dy;
                     if (qx < 0 || qy < 0 || qx >= width || qy >= height) continue;
@@ -211,6 +212,11 @@ int fastref_nms_mask(const uint16_t *score, int width, int height, uint8_t *mask
     return 0;
 }
 
+/* 3x3 non-maxima suppression (n = 1), the detector's default. */
+int fastref_nms_mask(const uint16_t *score, int width, int height, uint8_t *mask) {
+    return fastref_nms_mask_radius(score, width, height, 1, mask);
+}
+
 /* Grid-cell selection, "NMS-C" (Section II-B: one feature per cell, the one
  * with the highest score; Algorithm 1's last step) over all pyramid levels
  * with one shared grid (Section II-C: a level-k position scales up by 2^k to
@@ -218,11 +224,11 @@ int fastref_nms_mask(const uint16_t *score, int width, int height, uint8_t *mask
  * READING: cells are cell x cell level-0 pixels, partial cells at the right and
  * bottom edges are kept; ties across levels prefer the smaller level, ties
  * within a level the smaller row-major index; an empty cell gets the sentinel. */
-int fastref_detect_grid_kind(const fastref_plane *pyr, int levels, int t, int n, int cell, int kind,
-                             fastref_feature *out) {
+int fastref_detect_grid_nms(const fastref_plane *pyr, int levels, int t, int n, int cell, int kind,
+                            int radius, fastref_feature *out) {
     if (!pyr || !out || levels < 1 || levels > 8 || t < 0 || t > 255 || n < 1 || n > 16)
         return -1;
-    if (kind < FASTREF_SCORE_SADB || kind > FASTREF_SCORE_MT) return -1;
+    if (kind < FASTREF_SCORE_SADB || kind > FASTREF_SCORE_MT || radius < 1 || radius > 4) return -1;
     if (cell < 1 || cell % (1 << (levels - 1)) != 0) return -1;
     for (int k = 0; k < levels; ++k) {
         if (!plane_ok(&pyr[k])) return -1;
@@ -247,7 +253,7 @@ int fastref_detect_grid_kind(const fastref_plane *pyr, int levels, int t, int n,
         uint8_t *mask = (uint8_t *)malloc((size_t)w * (size_t)h);
         if (!score || !mask) { free(score); free(mask); return -1; }
         fastref_score_map_kind(img, t, n, kind, score);
-        fastref_nms_mask(score, w, h, mask);
+        fastref_nms_mask_radius(score, w, h, radius, mask);
         for (int y = 0; y < h; ++y) {
             for (int x = 0; x < w; ++x) {
                 if (!mask[(size_t)y * w + x]) continue;
@@ -274,7 +280,12 @@ int fastref_detect_grid_kind(const fastref_plane *pyr, int levels, int t, int n,
     return 0;
 }
 
+int fastref_detect_grid_kind(const fastref_plane *pyr, int levels, int t, int n, int cell, int kind,
+                             fastref_feature *out) {
+    return fastref_detect_grid_nms(pyr, levels, t, n, cell, kind, 1, out);
+}
+
 int fastref_detect_grid(const fastref_plane *pyr, int levels, int t, int n, int cell,
                         fastref_feature *out) {
-    return fastref_detect_grid_kind(pyr, levels, t, n, cell, FASTREF_SCORE_SADB, out);
+    return fastref_detect_grid_nms(pyr, levels, t, n, cell, FASTREF_SCORE_SADB, 1, out);
 }

@@ -83,6 +83,14 @@ int fastref_detect_grid(const fastref_plane *pyr, int levels, int t, int n, int 
 int fastref_detect_grid_kind(const fastref_plane *pyr, int levels, int t, int n, int cell, int kind,
                              fastref_feature *out);
 
+/* Non-maxima suppression over the (2r+1) x (2r+1) Moore neighbourhood, 1 <= r <= 4
+ * (Section I-B; fastref_nms_mask is r = 1), same tie rule. */
+int fastref_nms_mask_radius(const uint16_t *score, int width, int height, int r, uint8_t *mask);
+
+/* fastref_detect_grid_kind with NMS over (2r+1) x (2r+1) neighbourhoods. */
+int fastref_detect_grid_nms(const fastref_plane *pyr, int levels, int t, int n, int cell, int kind,
+                            int radius, fastref_feature *out);
+
 #ifdef __cplusplus
 }
 #endif

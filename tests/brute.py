@@ -110,21 +110,22 @@ def score_map(img: np.ndarray, t: int, n: int, kind: int = 0) -> np.ndarray:
     return out
 
 
-def nms(score: np.ndarray) -> np.ndarray:
+def nms(score: np.ndarray, r: int = 1) -> np.ndarray:
     h, w = score.shape
     idx = np.arange(h * w, dtype=np.int64).reshape(h, w)
     rank = score.astype(np.int64) * (h * w) + (h * w - 1 - idx)
-    pad = np.full((h + 2, w + 2), -1, np.int64)
-    pad[1:-1, 1:-1] = rank
+    pad = np.full((h + 2 * r, w + 2 * r), -1, np.int64)
+    pad[r:r + h, r:r + w] = rank
     keep = score > 0
-    for dy in (-1, 0, 1):
-        for dx in (-1, 0, 1):
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
             if dx or dy:
-                keep &= rank > pad[1 + dy:1 + dy + h, 1 + dx:1 + dx + w]
+                keep &= rank > pad[r + dy:r + dy + h, r + dx:r + dx + w]
     return keep
 
 
-def detect_grid(img: np.ndarray, levels: int, t: int, n: int, cell: int, kind: int = 0):
+def detect_grid(img: np.ndarray, levels: int, t: int, n: int, cell: int, kind: int = 0,
+                radius: int = 1):
     """img: (H, W) uint8 without padding.  Returns (slots list of tuples, planes)."""
     planes = pyramid(img, levels)
     H, W = img.shape
@@ -132,7 +133,7 @@ def detect_grid(img: np.ndarray, levels: int, t: int, n: int, cell: int, kind: i
     cands = []
     for k, P in enumerate(planes):
         s = score_map(P, t, n, kind)
-        keep = nms(s)
+        keep = nms(s, radius)
         ys, xs = np.nonzero(keep)
         for y, x in zip(ys.tolist(), xs.tolist()):
             cid = ((y << k) // cell) * gw + ((x << k) // cell)

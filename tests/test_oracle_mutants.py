@@ -30,6 +30,7 @@ MUTANTS = {
     "arc_sum_counts_off_arc": ("if (on_arc(bright, n, i)) arc_bright", "if ((bright >> i) & 1u) arc_bright"),
     "arc_sum_drops_dark": ("return arc_bright > arc_dark ? arc_bright : arc_dark;", "return arc_bright;"),
     "max_threshold_off_by_one": ("return d > t ? d : 0;", "return d > t ? d - 1 : 0;"),
+    "nms_radius_ignored": ("for (int dx = -r; dx <= r && keep; ++dx) {", "for (int dx = -1; dx <= 1 && keep; ++dx) {"),
     "max_threshold_short_window": ("            int q = v[(s + j) % 16];", "            if (j == n - 1) break;\n            int q = v[(s + j) % 16];"),
 }
 

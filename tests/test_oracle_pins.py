@@ -520,6 +520,60 @@ def test_score_kinds_brute_force_tiny_images(kind):
         assert as_tuples(got) == want, (trial, h, w, levels, t, n, cell)
 
 
+# ---------------------------------------------------------------- wider NMS
+
+def test_nms_radius_hand_cases():
+    """Section I-B: the neighbourhood has side 2r+1.  Two responses d pixels
+    apart both survive while r < d; from r = d on, the weaker one is suppressed,
+    and of two equal ones the earlier in row-major order survives."""
+    for d in (2, 3, 4):
+        s = np.zeros((12, 12), np.uint16)
+        s[5, 2] = 50
+        s[5, 2 + d] = 60
+        for r in range(1, 5):
+            m = oracle.nms_mask(s, r)
+            assert m[5, 2 + d] == 1
+            assert m[5, 2] == (1 if r < d else 0), (d, r)
+        s2 = np.zeros((12, 12), np.uint16)
+        s2[2, 5] = 70
+        s2[2 + d, 5 + d] = 70            # diagonal, equal scores
+        m = oracle.nms_mask(s2, d)
+        assert m[2, 5] == 1 and m[2 + d, 5 + d] == 0
+        m = oracle.nms_mask(s2, d - 1)
+        assert m[2, 5] == 1 and m[2 + d, 5 + d] == 1
+
+
+def test_nms_radius_nested_and_brute_force():
+    rng = np.random.default_rng(31)
+    for _ in range(40):
+        h, w = int(rng.integers(5, 30)), int(rng.integers(5, 30))
+        s = (rng.integers(0, 6, size=(h, w)) * rng.integers(0, 2, size=(h, w))).astype(np.uint16)
+        prev = None
+        for r in range(1, 5):
+            m = oracle.nms_mask(s, r).astype(bool)
+            assert np.array_equal(m, brute.nms(s, r)), r
+            if prev is not None:
+                assert not np.any(m & ~prev)     # a wider window never adds survivors
+            prev = m
+
+
+@pytest.mark.parametrize("radius", [2, 3, 4])
+def test_nms_radius_detect_grid_brute_force(radius):
+    rng = np.random.default_rng(400 + radius)
+    for trial in range(60):
+        h, w = int(rng.integers(8, 36)), int(rng.integers(8, 36))
+        levels = int(rng.integers(1, 3))
+        img = rng.integers(0, 256, size=(h, w)).astype(np.uint8)
+        if trial % 2:
+            img = (img // 85 * 85).astype(np.uint8)
+        t, n = int(rng.choice([0, 5, 20])), int(rng.integers(1, 13))
+        cell = (1 << (levels - 1)) * int(rng.integers(1, 4))
+        kind = trial % 3
+        got, _ = oracle.detect_grid(padded(img), w, levels, t, n, cell, kind, radius)
+        want, _ = brute.detect_grid(img, levels, t, n, cell, kind, radius)
+        assert as_tuples(got) == want, (trial, radius)
+
+
 def test_invalid_arguments_rejected():
     img = const_img(16, 16, 9)
     with pytest.raises(ValueError):
