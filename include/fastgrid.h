@@ -156,6 +156,30 @@ int fast_detect_grid(fast_ctx *ctx, const fast_plane *pyr, int levels, int t, in
 int fast_detect_grid_score(fast_ctx *ctx, const fast_plane *pyr, int levels, int t, int n,
                            int cell, int score, fast_feature *out, void *stream);
 
+/* The score stage alone (Section II-D): build levels 1..levels-1 into pyr[1..]
+ * as fast_detect_grid does, and write every level's corner scores of kind
+ * `score` (FAST_SCORE_*; 0 in the 3-pixel border and where the segment test
+ * fails) to maps[k], a device array of pyr[k].height rows of map_pitch[k]
+ * uint16 elements (map_pitch[k] >= pyr[k].width, maps 2-byte aligned;
+ * elements past the width are not written).  maps and map_pitch are host
+ * arrays of `levels` entries.  Enqueued on `stream`.
+ * Errors: as fast_detect_grid_score, and FAST_EINVAL for a NULL or misaligned
+ * map or a pitch below the level width. */
+int fast_score_maps(fast_ctx *ctx, const fast_plane *pyr, int levels, int t, int n, int score,
+                    uint16_t *const *maps, const int32_t *map_pitch, void *stream);
+
+/* Standalone non-maxima suppression over the (2 radius + 1)^2 Moore
+ * neighbourhood (Section I-B; radius 1..4, the paper's n) and the cell
+ * arg-max across levels (Sections II-B, II-C), from score maps laid out as
+ * fast_score_maps writes them for a level-0 size of width x height (level k
+ * is the floor halving k times).  Same tie rules and output slots as
+ * fast_detect_grid; with radius 1 the slots equal fast_detect_grid's.
+ * Errors: FAST_EINVAL for levels not in 1..8, sizes not in 1..65535, radius
+ * not in 1..4, a cell rule violation (as fast_detect_grid), NULL out, or a bad
+ * map (as fast_score_maps); FAST_EHIP if the launch fails. */
+int fast_nms_grid(fast_ctx *ctx, uint16_t *const *maps, const int32_t *map_pitch, int width,
+                  int height, int levels, int radius, int cell, fast_feature *out, void *stream);
+
 /* Batched path: all `njobs` requests (1..FAST_MAX_JOBS, any mix of sizes and
  * parameters) run in one persistent launch fed by a device-side work queue.
  * The job table and its work-item list are enqueued on `stream` as one copy

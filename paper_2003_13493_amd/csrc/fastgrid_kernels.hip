@@ -304,6 +304,11 @@ struct Geo {
 struct Params {
     int t, n, kc, k8;    // threshold, arc length, floor(N/4), floor(N/2)
     int kind;            // corner score kind (FAST_SCORE_*)
+    // score-map mode (smap[0] != null): the passes write each level's area
+    // scores to smap[l] (pitch spitch[l] elements) instead of running NMS;
+    // index l follows the levels handed to run_passes
+    uint16_t *smap[3];
+    int spitch[3];
     int cell;            // level-0 cell side
     int rx0, ry0;        // region origin in level-0 pixels
     int ncx;             // cells across the region
@@ -607,6 +612,18 @@ __device__ __forceinline__ LevelMap level_map(const Geo &g, int band_row, int ba
     return m;
 }
 
+// Write the scores of level g's sub-tile area from its LDS score map to a
+// global map (row y at dst + y * pitch elements).
+__device__ void store_scores(const uint8_t *smem, const Geo &g, uint16_t *dst, int pitch) {
+    const int w = g.ex - g.sx, h = g.ey - g.sy;
+    if (w <= 0 || h <= 0) return;
+    const uint16_t *m = (const uint16_t *)smem + (g.moff >> 1);
+    for (int i = threadIdx.x; i < w * h; i += blockDim.x) {
+        const int yy = div_small(i, w), xx = i - yy * w;
+        gstore<uint16_t>(dst + (ptrdiff_t)(g.sy + yy) * pitch + (g.sx + xx), m[(yy + 1) * g.mp + xx + 1]);
+    }
+}
+
 // Detect levels g0..g(nl-1) of the staged sub-tile (score maps zeroed) and
 // fold the survivors into the region's cell keys.  P1-P4 run on every wave
 // without workgroup barriers; one barrier makes all scores visible before
@@ -681,6 +698,13 @@ __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Ge
     before();
     __syncthreads();   // every level's scores, ring included, are in the maps
     after();
+    if (P.smap[0]) {   // score-map mode: the sub-tile's own scores, no NMS
+        store_scores(smem, g0, P.smap[0], P.spitch[0]);
+        if (nl > 1) store_scores(smem, g1, P.smap[1], P.spitch[1]);
+        if (nl > 2) store_scores(smem, g2, P.smap[2], P.spitch[2]);
+        __builtin_amdgcn_s_setprio(0);
+        return;
+    }
     // P5: 3x3 NMS of the sub-tile's own pixels, then the cell keys
     for (int i = lane; i < n2; i += 64) {
         const uint16_t e = list[i];
@@ -949,7 +973,12 @@ __device__ void process_subtile_upper(const fg_job &J, int sx0, int sy0, int xr1
         g.moff = OFF_M0;
         g.mp = M0_P;
         set_groups(g);
-        run_passes(smem, g, g, g, 1, P, (uint32_t *)(smem + OFF_KEYS));
+        Params Pk = P;
+        if (P.smap[0]) {
+            Pk.smap[0] = J.smap[k];
+            Pk.spitch[0] = J.smap_pitch[k];
+        }
+        run_passes(smem, g, g, g, 1, Pk, (uint32_t *)(smem + OFF_KEYS));
     }
 }
 
@@ -970,6 +999,8 @@ __device__ __forceinline__ Region region_of(const fg_job &J, int region) {
     R.P.t = J.t;
     R.P.n = J.n;
     R.P.kind = J.score;
+    R.P.smap[0] = R.P.smap[1] = R.P.smap[2] = nullptr;
+    R.P.spitch[0] = R.P.spitch[1] = R.P.spitch[2] = 0;
     R.P.kc = J.n >> 2;
     R.P.k8 = J.n >> 1;
     R.P.cell = J.cell;
@@ -1140,6 +1171,103 @@ __device__ __forceinline__ int xcd_item(int b, int n) {
     const int q = n >> 3, r = n & 7;
     const int xcd = b & 7, local = b >> 3;
     return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+// Score-map mode of a region: levels 0 .. F-1 from one load, no cell keys.
+__device__ void scores_region(const fg_job &J, int region, uint8_t *smem) {
+    const Region R = region_of(J, region);
+    Params P = R.P;
+    for (int l = 0; l < MAX_FUSED; ++l) {
+        P.smap[l] = J.smap[l < J.levels ? l : 0];
+        P.spitch[l] = J.smap_pitch[l < J.levels ? l : 0];
+    }
+    for (int sy0 = P.ry0; sy0 < R.yr1; sy0 += SUB)
+        for (int sx0 = P.rx0; sx0 < R.xr1; sx0 += SUB) process_subtile(J, sx0, sy0, R.xr1, R.yr1, P, smem);
+}
+
+// Score-map mode of levels MAX_FUSED.. of a region.
+__device__ void scores_region_upper(const fg_job &J, int region, uint8_t *smem) {
+    const Region R = region_of(J, region);
+    Params P = R.P;
+    P.smap[0] = J.smap[MAX_FUSED];   // non-null selects the mode; each level sets its own
+    for (int sy0 = P.ry0; sy0 < R.yr1; sy0 += SUB)
+        for (int sx0 = P.rx0; sx0 < R.xr1; sx0 += SUB) process_subtile_upper(J, sx0, sy0, R.xr1, R.yr1, P, smem);
+}
+
+// Standalone NMS over (2r+1) x (2r+1) neighbourhoods and the cell arg-max
+// across levels, from global score maps (J.smap).  One workgroup per region;
+// each level's part of the region is walked in 64 x 64 tiles staged in LDS
+// with an r-pixel halo (zero outside the map).
+constexpr int NMS_TILE = 64 + 2 * 4;
+constexpr int NMS_KEYS_OFF = (NMS_TILE * NMS_TILE * 2 + 15) & ~15;
+size_t nms_smem_bytes() { return (size_t)NMS_KEYS_OFF + MAX_KEYS * 4; }
+
+__global__ void __launch_bounds__(512) nms_grid_kernel(fg_job J, int radius) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const int region = xcd_item(blockIdx.x, gridDim.x);
+    const Region R = region_of(J, region);
+    uint16_t *tile = (uint16_t *)smem;
+    uint32_t *keys = (uint32_t *)(smem + NMS_KEYS_OFF);
+    keys_clear(keys, R.ncx * R.ncy);
+    const int r = radius;
+    for (int k = 0; k < J.levels; ++k) {
+        const int x0 = R.P.rx0 >> k, y0 = R.P.ry0 >> k;
+        const int x1 = min(R.xr1 >> k, J.w[k]), y1 = min(R.yr1 >> k, J.h[k]);
+        const int cw = J.cell >> k;
+        const uint16_t *map = J.smap[k];
+        const int mp = J.smap_pitch[k];
+        for (int ty0 = y0; ty0 < y1; ty0 += SUB) {
+            for (int tx0 = x0; tx0 < x1; tx0 += SUB) {
+                const int tw = min(SUB, x1 - tx0), th = min(SUB, y1 - ty0);
+                const int TW = tw + 2 * r, TH = th + 2 * r;
+                __syncthreads();   // the previous tile has been read
+                for (int i = threadIdx.x; i < TW * TH; i += blockDim.x) {
+                    const int yy = div_small(i, TW), xx = i - yy * TW;
+                    const int gx = tx0 - r + xx, gy = ty0 - r + yy;
+                    tile[i] = gx >= 0 && gx < J.w[k] && gy >= 0 && gy < J.h[k]
+                                  ? gload<uint16_t>(map + (ptrdiff_t)gy * mp + gx) : (uint16_t)0;
+                }
+                __syncthreads();
+                for (int i = threadIdx.x; i < tw * th; i += blockDim.x) {
+                    const int yy = div_small(i, tw), xx = i - yy * tw;
+                    const uint16_t *q = tile + (yy + r) * TW + (xx + r);
+                    const uint32_t s = q[0];
+                    if (s == 0) continue;
+                    // earlier neighbours in row-major order must be strictly
+                    // lower, later ones lower or equal
+                    bool keep = true;
+                    for (int dy = -r; dy <= r && keep; ++dy)
+                        for (int dx = -r; dx <= r; ++dx) {
+                            if (dx == 0 && dy == 0) continue;
+                            const uint32_t v = q[dy * TW + dx];
+                            const bool earlier = dy < 0 || (dy == 0 && dx < 0);
+                            if (earlier ? v >= s : v > s) {
+                                keep = false;
+                                break;
+                            }
+                        }
+                    if (!keep) continue;
+                    const int ox = tx0 + xx - x0, oy = ty0 + yy - y0;
+                    const int cx = div_small(ox, cw), cy = div_small(oy, cw);
+                    const uint32_t local = (uint32_t)((oy - cy * cw) * cw + (ox - cx * cw));
+                    const uint32_t key = (s << 19) | ((uint32_t)(7 - k) << 16) | (0xFFFFu - local);
+                    atomicMax(&keys[cy * R.ncx + cx], key);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    keys_write(J, R, keys);
+}
+
+__global__ void __launch_bounds__(512) score_plain_kernel(fg_job J) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    scores_region(J, xcd_item(blockIdx.x, gridDim.x), smem);
+}
+
+__global__ void __launch_bounds__(512) score_upper_plain_kernel(fg_job J) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    scores_region_upper(J, xcd_item(blockIdx.x, gridDim.x), smem);
 }
 
 __global__ void __launch_bounds__(512) detect_plain_kernel(fg_job J) {
@@ -1375,6 +1503,27 @@ hipError_t fg_launch_plain(const fg_job &j, const fg_launch &L, hipStream_t s) {
     }
     hipLaunchKernelGGL(detect_upper_plain_kernel, dim3(j.rx * j.ry), dim3(L.block),
                        fg_smem_bytes(L.block), s, j);
+    return hipGetLastError();
+}
+
+hipError_t fg_launch_score_maps(const fg_job &j, const fg_launch &L, hipStream_t s) {
+    hipLaunchKernelGGL(score_plain_kernel, dim3(j.rx * j.ry), dim3(L.block), fg_smem_bytes(L.block), s, j);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || j.levels <= MAX_FUSED) return e;
+    for (int k = MAX_FUSED; k < j.levels; ++k) {
+        dim3 grid(((j.w[k] + 3) / 4 + 63) / 64, j.h[k]);
+        hipLaunchKernelGGL(pyr_kernel, grid, dim3(64), 0, s, j.lvl[k - 1], j.pitch[k - 1], j.lvl[k],
+                           j.w[k], j.h[k], j.pitch[k]);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(score_upper_plain_kernel, dim3(j.rx * j.ry), dim3(L.block), fg_smem_bytes(L.block),
+                       s, j);
+    return hipGetLastError();
+}
+
+hipError_t fg_launch_nms_grid(const fg_job &j, int radius, hipStream_t s) {
+    hipLaunchKernelGGL(nms_grid_kernel, dim3(j.rx * j.ry), dim3(256), nms_smem_bytes(), s, j, radius);
     return hipGetLastError();
 }
 

@@ -118,13 +118,13 @@ int check_params(fast_ctx *c, int levels, int t, int n, int cell) {
 }
 
 int make_job(fast_ctx *c, const fast_plane *pyr, int levels, int t, int n, int cell, int score,
-             fast_feature *out, fg_job &j) {
+             fast_feature *out, fg_job &j, bool need_out = true) {
     int rc = check_pyr(c, pyr, levels);
     if (rc) return rc;
     rc = check_params(c, levels, t, n, cell);
     if (rc) return rc;
     if (score < FAST_SCORE_SADB || score > FAST_SCORE_MT) return fail(c, FAST_EINVAL, "unknown score kind");
-    if (!out) return fail(c, FAST_EINVAL, "out is NULL");
+    if (!out && need_out) return fail(c, FAST_EINVAL, "out is NULL");
     memset(&j, 0, sizeof(j));
     for (int k = 0; k < levels; ++k) {
         j.lvl[k] = pyr[k].data;
@@ -358,6 +358,73 @@ FG_API int fast_detect_grid_score(fast_ctx *c, const fast_plane *pyr, int levels
     DeviceGuard g(c->device);
     hipError_t e = fg_launch_plain(j, c->launch, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "detect launch");
+    return FAST_OK;
+}
+
+// Score maps of levels 0..levels-1 with floor-halved sizes of width x height.
+int check_maps(fast_ctx *c, uint16_t *const *maps, const int32_t *pitch, int width, int height, int levels) {
+    if (!maps || !pitch) return fail(c, FAST_EINVAL, "maps or map_pitch is NULL");
+    int w = width, h = height;
+    for (int k = 0; k < levels; ++k) {
+        if (w < 1 || h < 1) return fail(c, FAST_EINVAL, "level " + std::to_string(k) + " has zero size");
+        if (!maps[k]) return fail(c, FAST_EINVAL, "map " + std::to_string(k) + " is NULL");
+        if (((uintptr_t)maps[k] & 1u) != 0) return fail(c, FAST_EINVAL, "map not 2-byte aligned");
+        if (pitch[k] < w) return fail(c, FAST_EINVAL, "map pitch < level width");
+        w >>= 1;
+        h >>= 1;
+    }
+    return FAST_OK;
+}
+
+FG_API int fast_score_maps(fast_ctx *c, const fast_plane *pyr, int levels, int t, int n, int score,
+                           uint16_t *const *maps, const int32_t *map_pitch, void *stream) {
+    if (!c) return FAST_EINVAL;
+    fg_job j;
+    // any valid cell: it only shapes the work decomposition here
+    int rc = make_job(c, pyr, levels, t, n, 1 << (levels - 1 < 4 ? 4 : levels - 1), score, nullptr, j, false);
+    if (rc) return rc;
+    rc = check_maps(c, maps, map_pitch, pyr[0].width, pyr[0].height, levels);
+    if (rc) return rc;
+    for (int k = 0; k < levels; ++k) {
+        j.smap[k] = maps[k];
+        j.smap_pitch[k] = map_pitch[k];
+    }
+    DeviceGuard g(c->device);
+    hipError_t e = fg_launch_score_maps(j, c->launch, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "score map launch");
+    return FAST_OK;
+}
+
+FG_API int fast_nms_grid(fast_ctx *c, uint16_t *const *maps, const int32_t *map_pitch, int width, int height,
+                         int levels, int radius, int cell, fast_feature *out, void *stream) {
+    if (!c) return FAST_EINVAL;
+    if (levels < 1 || levels > FAST_MAX_LEVELS) return fail(c, FAST_EINVAL, "levels not in 1..8");
+    if (width < 1 || height < 1 || width > 65535 || height > 65535)
+        return fail(c, FAST_EINVAL, "width or height not in 1..65535");
+    if (radius < 1 || radius > 4) return fail(c, FAST_EINVAL, "radius not in 1..4");
+    int rc = check_params(c, levels, 0, 1, cell);
+    if (rc) return rc;
+    if (!out) return fail(c, FAST_EINVAL, "out is NULL");
+    rc = check_maps(c, maps, map_pitch, width, height, levels);
+    if (rc) return rc;
+    fg_job j;
+    memset(&j, 0, sizeof(j));
+    int w = width, h = height;
+    for (int k = 0; k < levels; ++k) {
+        j.w[k] = w;
+        j.h[k] = h;
+        j.smap[k] = maps[k];
+        j.smap_pitch[k] = map_pitch[k];
+        w >>= 1;
+        h >>= 1;
+    }
+    j.levels = levels;
+    j.cell = cell;
+    j.out = out;
+    fg_job_layout(j, c->launch);
+    DeviceGuard g(c->device);
+    hipError_t e = fg_launch_nms_grid(j, radius, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "nms launch");
     return FAST_OK;
 }
 

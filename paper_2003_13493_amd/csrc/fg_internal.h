@@ -15,6 +15,8 @@ struct fg_job {
     int32_t pitch[FAST_MAX_LEVELS];
     int32_t levels, t, n, cell;
     int32_t score;                   // corner score kind (FAST_SCORE_*)
+    uint16_t *smap[FAST_MAX_LEVELS]; // score maps (score-map and standalone-NMS entry points)
+    int32_t smap_pitch[FAST_MAX_LEVELS];   // their pitches in elements
     fast_feature *out;               // gw*gh slots
     int32_t gw, gh;                  // grid size in cells
     int32_t rcells;                  // cells per region side
@@ -41,6 +43,14 @@ hipError_t fg_launch_plain(const fg_job &j, const fg_launch &L, hipStream_t s);
 
 // Pyramid only, one frame.
 hipError_t fg_launch_pyramid(const fg_job &j, hipStream_t s);
+
+// One frame's score maps (j.smap): builds levels 1.. like fg_launch_plain and
+// writes every level's scores instead of selecting features.
+hipError_t fg_launch_score_maps(const fg_job &j, const fg_launch &L, hipStream_t s);
+
+// Standalone NMS over (2 radius + 1)^2 neighbourhoods and the cell arg-max
+// from j.smap (j.lvl unused) into j.out.
+hipError_t fg_launch_nms_grid(const fg_job &j, int radius, hipStream_t s);
 
 // Words of the persistent batched kernel's counter buffer: the queue head and
 // the exit count (the rest is padding).

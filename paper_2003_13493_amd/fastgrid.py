@@ -31,7 +31,7 @@ FAST_SCORE_SADB, FAST_SCORE_SADA, FAST_SCORE_MT = 0, 1, 2
 
 EXPORTS = ("fast_ctx_create", "fast_ctx_destroy", "fast_strerror", "fast_last_error",
            "fast_pyr_dims", "fast_grid_dims", "fast_pyr_build", "fast_detect_grid",
-           "fast_detect_grid_score",
+           "fast_detect_grid_score", "fast_score_maps", "fast_nms_grid",
            "fast_submit", "fast_poll", "fast_wait", "fast_plan_create", "fast_plan_launch",
            "fast_plan_destroy", "fast_set_launch")
 
@@ -86,6 +86,9 @@ def load() -> ctypes.CDLL:
             "fast_plan_launch": ([vp, i32, vp, u64p], i32),
             "fast_plan_destroy": ([vp, i32], i32),
             "fast_set_launch": ([vp, i32, i32, i32], i32),
+            "fast_score_maps": ([vp, P, i32, i32, i32, i32, ctypes.POINTER(vp), ctypes.POINTER(i32), vp], i32),
+            "fast_nms_grid": ([vp, ctypes.POINTER(vp), ctypes.POINTER(i32), i32, i32, i32, i32, i32, vp, vp],
+                              i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -232,6 +235,37 @@ class Pyramid:
         return self.tensors[k][:, :w].cpu().numpy()
 
 
+def fast_score_maps(ctx, planes, levels: int, t: int, n: int, score: int, maps, pitches,
+                    stream=None) -> None:
+    _check(ctx, load().fast_score_maps(ctx, planes, levels, t, n, score, maps, pitches, _stream(stream)),
+           "fast_score_maps")
+
+
+def fast_nms_grid(ctx, maps, pitches, width: int, height: int, levels: int, radius: int, cell: int,
+                  out_ptr: int, stream=None) -> None:
+    _check(ctx, load().fast_nms_grid(ctx, maps, pitches, width, height, levels, radius, cell, out_ptr,
+                                     _stream(stream)), "fast_nms_grid")
+
+
+class ScoreMaps:
+    """Device score maps of a pyramid: one (H_k, W_k) tensor of uint16 scores per
+    level (held as int16), for fast_score_maps / fast_nms_grid."""
+
+    def __init__(self, width: int, height: int, levels: int, device="cuda"):
+        import torch
+        self.width, self.height, self.levels = width, height, levels
+        self.tensors = []
+        w, h = width, height
+        for _ in range(levels):
+            self.tensors.append(torch.zeros((h, w), dtype=torch.int16, device=device))
+            w, h = w // 2, h // 2
+        self.ptrs = (ctypes.c_void_p * levels)(*[t.data_ptr() for t in self.tensors])
+        self.pitches = (ctypes.c_int32 * levels)(*[t.shape[1] for t in self.tensors])
+
+    def level(self, k: int) -> np.ndarray:
+        return self.tensors[k].cpu().numpy().view(np.uint16)
+
+
 class Grid:
     """Device array of cell slots for one frame."""
 
@@ -278,6 +312,14 @@ class Context:
         else:
             fast_detect_grid_score(self.handle, pyr.planes, pyr.levels, t, n, cell, score, grid.ptr,
                                    stream)
+
+    def score_maps(self, pyr: Pyramid, t: int, n: int, maps: ScoreMaps, score: int = FAST_SCORE_SADB,
+                   stream=None) -> None:
+        fast_score_maps(self.handle, pyr.planes, pyr.levels, t, n, score, maps.ptrs, maps.pitches, stream)
+
+    def nms_grid(self, maps: ScoreMaps, radius: int, cell: int, grid: Grid, stream=None) -> None:
+        fast_nms_grid(self.handle, maps.ptrs, maps.pitches, maps.width, maps.height, maps.levels, radius,
+                      cell, grid.ptr, stream)
 
     @staticmethod
     def make_jobs(items) -> ctypes.Array:
