@@ -110,6 +110,40 @@ def copy_bandwidth(nbytes: int) -> float:
     return 2 * nbytes / (ms / 1e3) / 1e9
 
 
+def nms_radius_sweep(ctx, spec, reps: int = 200) -> dict:
+    """The paper's NMS sweep (Table III: NMS with cell maximum, n = 1..4) on one
+    frame: the score stage alone (fast_score_maps), then the standalone NMS and
+    cell arg-max (fast_nms_grid) at radius 1..4, and the fused path
+    (fast_detect_grid) for comparison.  Kernel time per frame from events around
+    `reps` back-to-back launches on the current stream."""
+    import torch
+    from paper_2003_13493_amd import fastgrid
+    pyr = fastgrid.Pyramid(spec.width, spec.height, spec.levels)
+    pyr.upload(spec.make())
+    maps = fastgrid.ScoreMaps(spec.width, spec.height, spec.levels)
+    grid = fastgrid.Grid(spec.width, spec.height, spec.cell)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn) -> float:
+        for _ in range(10):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return round(e0.elapsed_time(e1) / reps * 1e3, 2)
+
+    out = {"workload": f"{spec.width}x{spec.height}, {spec.levels} levels, t={spec.t}, N={spec.n}, "
+                       f"{spec.cell}x{spec.cell} cells; microseconds per frame",
+           "score_maps_us": timed(lambda: ctx.score_maps(pyr, spec.t, spec.n, maps))}
+    for r in (1, 2, 3, 4):
+        out[f"nms_grid_r{r}_us"] = timed(lambda: ctx.nms_grid(maps, r, spec.cell, grid))
+    out["fused_detect_r1_us"] = timed(lambda: ctx.detect(pyr, spec.t, spec.n, spec.cell, grid))
+    return out
+
+
 def plain_latency(ctx, spec, nframes: int) -> dict:
     """One frame at a time through the plain path with a host sync after each:
     upload from pinned memory, detect, download of the cell slots; stage times
@@ -370,6 +404,8 @@ def main() -> int:
                         ("1920x1080_L4", synth.PLAIN_1080)):
         latency[name] = plain_latency(ctx, lspec, args.plain_latency_frames)
         log(f"plain latency {name}: {latency[name]['upload_detect_download_ms']}")
+    nms_sweep = nms_radius_sweep(ctx, synth.PLAIN_752)
+    log(f"NMS radius sweep: {nms_sweep}")
     copy_gbs = copy_bandwidth(1 << 30)
 
     achieved = bytes_per_step / (ms_per_step / 1e3) / 1e9
@@ -409,6 +445,7 @@ def main() -> int:
         "graph_replay_ms_per_step": round(graph_ms, 5),
         "score_kinds_ms_per_step": {"workload": "the same batch with every job scored as SAD-B (the "
                                                 "headline), SAD-A or MT", **kinds_ms},
+        "nms_radius_sweep": nms_sweep,
         "step_ms_p50": round(float(np.percentile(step_ms, 50)), 5),
         "step_ms_p99": round(float(np.percentile(step_ms, 99)), 5),
         "plain": {

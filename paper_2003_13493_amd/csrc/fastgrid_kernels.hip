@@ -1197,16 +1197,23 @@ __device__ void scores_region_upper(const fg_job &J, int region, uint8_t *smem) 
 // Standalone NMS over (2r+1) x (2r+1) neighbourhoods and the cell arg-max
 // across levels, from global score maps (J.smap).  One workgroup per region;
 // each level's part of the region is walked in 64 x 64 tiles staged in LDS
-// with an r-pixel halo (zero outside the map).
-constexpr int NMS_TILE = 64 + 2 * 4;
-constexpr int NMS_KEYS_OFF = (NMS_TILE * NMS_TILE * 2 + 15) & ~15;
+// with an r-pixel halo (zero outside the map).  Every tile pixel gets the
+// rank (score << 16) | (0xFFFF - its row-major index in the tile) (0 for
+// score 0): ranks are unique, and a higher rank means a higher score or, on
+// a tie, an earlier pixel, so a pixel survives exactly when its rank is the
+// maximum of its window.  The window maximum is separable: a row pass, then
+// a column pass, 2(2r+1) comparisons per pixel.
+constexpr int NMS_TILE = SUB + 2 * 4;
+constexpr int NMS_HMAX_OFF = NMS_TILE * NMS_TILE * 4;
+constexpr int NMS_KEYS_OFF = NMS_HMAX_OFF + NMS_TILE * SUB * 4;
 size_t nms_smem_bytes() { return (size_t)NMS_KEYS_OFF + MAX_KEYS * 4; }
 
 __global__ void __launch_bounds__(512) nms_grid_kernel(fg_job J, int radius) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     const int region = xcd_item(blockIdx.x, gridDim.x);
     const Region R = region_of(J, region);
-    uint16_t *tile = (uint16_t *)smem;
+    uint32_t *rank = (uint32_t *)smem;
+    uint32_t *hmax = (uint32_t *)(smem + NMS_HMAX_OFF);
     uint32_t *keys = (uint32_t *)(smem + NMS_KEYS_OFF);
     keys_clear(keys, R.ncx * R.ncy);
     const int r = radius;
@@ -1224,33 +1231,33 @@ __global__ void __launch_bounds__(512) nms_grid_kernel(fg_job J, int radius) {
                 for (int i = threadIdx.x; i < TW * TH; i += blockDim.x) {
                     const int yy = div_small(i, TW), xx = i - yy * TW;
                     const int gx = tx0 - r + xx, gy = ty0 - r + yy;
-                    tile[i] = gx >= 0 && gx < J.w[k] && gy >= 0 && gy < J.h[k]
-                                  ? gload<uint16_t>(map + (ptrdiff_t)gy * mp + gx) : (uint16_t)0;
+                    const uint32_t sc = gx >= 0 && gx < J.w[k] && gy >= 0 && gy < J.h[k]
+                                            ? gload<uint16_t>(map + (ptrdiff_t)gy * mp + gx) : 0u;
+                    rank[i] = sc ? (sc << 16) | (0xFFFFu - (uint32_t)i) : 0u;
                 }
                 __syncthreads();
+                // row pass: the maximum over columns xx-r .. xx+r of every row
+                for (int i = threadIdx.x; i < tw * TH; i += blockDim.x) {
+                    const int yy = div_small(i, tw), xx = i - yy * tw;
+                    const uint32_t *q = rank + yy * TW + xx;   // columns xx .. xx+2r
+                    uint32_t m = q[0];
+                    for (int d = 1; d <= 2 * r; ++d) m = max(m, q[d]);
+                    hmax[i] = m;
+                }
+                __syncthreads();
+                // column pass over the tile's own pixels, then the cell keys
                 for (int i = threadIdx.x; i < tw * th; i += blockDim.x) {
                     const int yy = div_small(i, tw), xx = i - yy * tw;
-                    const uint16_t *q = tile + (yy + r) * TW + (xx + r);
-                    const uint32_t s = q[0];
-                    if (s == 0) continue;
-                    // earlier neighbours in row-major order must be strictly
-                    // lower, later ones lower or equal
-                    bool keep = true;
-                    for (int dy = -r; dy <= r && keep; ++dy)
-                        for (int dx = -r; dx <= r; ++dx) {
-                            if (dx == 0 && dy == 0) continue;
-                            const uint32_t v = q[dy * TW + dx];
-                            const bool earlier = dy < 0 || (dy == 0 && dx < 0);
-                            if (earlier ? v >= s : v > s) {
-                                keep = false;
-                                break;
-                            }
-                        }
-                    if (!keep) continue;
+                    const uint32_t own = rank[(yy + r) * TW + xx + r];
+                    if (own == 0) continue;
+                    uint32_t m = 0;
+                    for (int d = 0; d <= 2 * r; ++d) m = max(m, hmax[(yy + d) * tw + xx]);
+                    if (m != own) continue;
+                    const uint32_t sc = own >> 16;
                     const int ox = tx0 + xx - x0, oy = ty0 + yy - y0;
                     const int cx = div_small(ox, cw), cy = div_small(oy, cw);
                     const uint32_t local = (uint32_t)((oy - cy * cw) * cw + (ox - cx * cw));
-                    const uint32_t key = (s << 19) | ((uint32_t)(7 - k) << 16) | (0xFFFFu - local);
+                    const uint32_t key = (sc << 19) | ((uint32_t)(7 - k) << 16) | (0xFFFFu - local);
                     atomicMax(&keys[cy * R.ncx + cx], key);
                 }
             }
