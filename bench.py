@@ -275,6 +275,8 @@ def main() -> int:
                     help="also run device-to-device copies of this size (counter calibration)")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="seconds of Poisson arrivals per serving mode (0 skips serving)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the score-kind and NMS-radius sweeps (profiling runs of the headline kernel)")
     ap.add_argument("--launch", type=str, default="",
                     help="region,block,blocks_per_cu launch shape (default: library default)")
     args = ap.parse_args()
@@ -363,7 +365,8 @@ def main() -> int:
     # ---- the same batch with the paper's other corner scores (Section II-D):
     # each kind gets its own resident plans over the same frames and outputs
     kinds_ms = {"sadb": round(ms_per_step, 5)}
-    for name, kind in (("sada", fastgrid.FAST_SCORE_SADA), ("mt", fastgrid.FAST_SCORE_MT)):
+    for name, kind in () if args.no_extras else (("sada", fastgrid.FAST_SCORE_SADA),
+                                                  ("mt", fastgrid.FAST_SCORE_MT)):
         kplans = []
         for inst in insts:
             kjobs = fastgrid.Context.make_jobs(
@@ -404,7 +407,7 @@ def main() -> int:
                         ("1920x1080_L4", synth.PLAIN_1080)):
         latency[name] = plain_latency(ctx, lspec, args.plain_latency_frames)
         log(f"plain latency {name}: {latency[name]['upload_detect_download_ms']}")
-    nms_sweep = nms_radius_sweep(ctx, synth.PLAIN_752)
+    nms_sweep = None if args.no_extras else nms_radius_sweep(ctx, synth.PLAIN_752)
     log(f"NMS radius sweep: {nms_sweep}")
     copy_gbs = copy_bandwidth(1 << 30)
 
