@@ -173,6 +173,31 @@ def test_batch_single_subtile_regions_of_mixed_sides(ctx):
         check_all(specs, pyrs, grids, want, f"mixed sides round {r}")
 
 
+def test_submit_grows_its_staging_buffer(ctx):
+    """Two 4096x2160 frames with 16-pixel regions are about 69,000 work items,
+    more than a submission slot first holds: the job table and items move to
+    larger pinned and device buffers, and the result stays exact.  A small
+    submission afterwards reuses the grown slot."""
+    specs = [synth.FrameSpec(4096, 2160, 3, 12, 9, 16, seed=1500 + i, nshapes=150, sigma=4.0)
+             for i in range(2)]
+    frames = [s.make() for s in specs]
+    want = []
+    for s, img in zip(specs, frames):
+        slots, planes = oracle.detect_grid(img, s.width, s.levels, s.t, s.n, s.cell)
+        want.append((slots, [p[:, :pw].copy() for p, pw in planes]))
+    print("case large submission", flush=True)
+    try:
+        ctx.set_launch(16, 256, 3)
+        for rnd in range(2):
+            sp, fr, wt = (specs, frames, want) if rnd == 0 else (specs[:1], frames[:1], want[:1])
+            pyrs, grids, jobs = make_resident(sp, fr)
+            tk = ctx.submit(jobs)
+            assert ctx.wait(tk, 60_000)
+            check_all(sp, pyrs, grids, wt, f"large submission round {rnd}")
+    finally:
+        ctx.set_launch(64, 256, 3)
+
+
 def test_plan_rejects_unknown_flags(ctx, batch):
     specs, frames, _ = batch
     pyrs, grids, jobs = make_resident(specs[:2], frames[:2])
