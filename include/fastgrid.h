@@ -223,7 +223,11 @@ int fast_plan_destroy(fast_ctx *ctx, int plan_id);
 
 /* Launch-shape tuning (the autotuner's knobs), per context.
  * region: side of the square region one workgroup owns, in level-0 pixels,
- *         rounded up to a multiple of the cell (16..256);
+ *         rounded up to a multiple of the cell (16..256), for every entry
+ *         point; 0 restores the default of a new context: 64, except that
+ *         a one-frame call (fast_detect_grid*, fast_score_maps,
+ *         fast_nms_grid) on a frame of at most 3 levels with fewer 64-pixel
+ *         regions than half the compute units uses 32 (faster there);
  * block:  threads per workgroup, a multiple of 64 in 64..512;
  * persistent_blocks_per_cu: workgroups per compute unit for the persistent
  *         batched kernel (1..16).

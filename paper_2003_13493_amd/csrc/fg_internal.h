@@ -26,7 +26,8 @@ struct fg_job {
 
 // Launch shape knobs (set per context by fast_set_launch / the autotuner).
 struct fg_launch {
-    int region;          // target region side in level-0 pixels
+    int region;          // target region side in level-0 pixels, batches
+    int plain_region;    // the same for one-frame calls; 0 = chosen per frame
     int block;           // threads per workgroup
     int blocks_per_cu;   // persistent kernel occupancy target
     int num_cu;          // compute units on the device

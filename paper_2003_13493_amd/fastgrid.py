@@ -300,7 +300,12 @@ class Context:
             pass
 
     def set_launch(self, region: int, block: int, blocks_per_cu: int) -> None:
+        """region 0 selects the default: 64, or 32 for one small frame."""
         fast_set_launch(self.handle, region, block, blocks_per_cu)
+
+    def reset_launch(self) -> None:
+        """The launch shape of a new context."""
+        fast_set_launch(self.handle, 0, 256, 3)
 
     def pyr_build(self, pyr: Pyramid, stream=None) -> None:
         fast_pyr_build(self.handle, pyr.planes, pyr.levels, stream)

@@ -9,6 +9,7 @@ of back-to-back launches of a resident plan, measured with device events.
 
 Results are cached as JSON keyed by the workload signature (frame sizes,
 levels, cells), so a serving process can load the tuned shape at start-up.
+The chosen shape is applied to the context, one-frame calls included.
 """
 from __future__ import annotations
 

@@ -195,7 +195,7 @@ def test_submit_grows_its_staging_buffer(ctx):
             assert ctx.wait(tk, 60_000)
             check_all(sp, pyrs, grids, wt, f"large submission round {rnd}")
     finally:
-        ctx.set_launch(64, 256, 3)
+        ctx.reset_launch()
 
 
 def test_plan_rejects_unknown_flags(ctx, batch):
@@ -266,4 +266,4 @@ def test_batch_launch_shapes_with_deep_levels(ctx, shape):
         assert ctx.wait(tk, 60_000)
         check_all(specs, pyrs, grids, want, f"shape {shape}")
     finally:
-        ctx.set_launch(64, 256, 3)
+        ctx.reset_launch()

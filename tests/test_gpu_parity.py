@@ -108,19 +108,20 @@ def test_launch_shapes_agree(ctx):
     img = spec.make()
     want, _ = oracle.detect_grid(img, spec.width, spec.levels, spec.t, spec.n, spec.cell)
     try:
-        for region, block in ((32, 64), (64, 256), (128, 512), (256, 128), (96, 128)):
+        for region, block in ((32, 64), (64, 256), (128, 512), (256, 128), (96, 128), (0, 256), (16, 256)):
             ctx.set_launch(region, block, 4)
             got, _ = run_plain(ctx, img, spec.width, spec.levels, spec.t, spec.n, spec.cell)
             assert np.array_equal(got, want), (region, block)
     finally:
-        ctx.set_launch(64, 256, 3)
+        ctx.reset_launch()
 
 
 def test_set_launch_rejects_bad_shapes(ctx):
     """Blocks must be multiples of 64 in 64..512, regions 16..256, 1..16
-    workgroups per CU; a rejected shape leaves the previous one in force."""
+    workgroups per CU (region 0: the defaults); a rejected shape leaves the
+    previous one in force."""
     try:
-        for region, block, bpc in ((64, 100, 3), (64, 0, 3), (64, 576, 3), (8, 256, 3), (300, 256, 3),
+        for region, block, bpc in ((64, 100, 3), (64, 0, 3), (64, 576, 3), (8, 256, 3), (300, 256, 3), (-1, 256, 3),
                                    (64, 256, 0), (64, 256, 17)):
             with pytest.raises(fastgrid.FastError) as ei:
                 ctx.set_launch(region, block, bpc)
@@ -128,7 +129,7 @@ def test_set_launch_rejects_bad_shapes(ctx):
         for block in (192, 320, 448):
             ctx.set_launch(64, block, 2)
     finally:
-        ctx.set_launch(64, 256, 3)
+        ctx.reset_launch()
     spec = synth.PLAIN_320
     img = spec.make()
     want, _ = oracle.detect_grid(img, spec.width, spec.levels, spec.t, spec.n, spec.cell)

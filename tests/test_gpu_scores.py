@@ -100,7 +100,7 @@ def test_batch_mixed_score_kinds(ctx, shape):
         tk = ctx.submit(jobs)
         assert ctx.wait(tk, 60_000)
     finally:
-        ctx.set_launch(64, 256, 3)
+        ctx.reset_launch()
     for i, (s, p, g) in enumerate(zip(specs, pyrs, grids)):
         slots, planes = want[i]
         for k in range(1, s.levels):
