@@ -59,6 +59,39 @@ def cpu_baseline(specs, frames, budget_s: float) -> dict:
                       f"{t_total:.1f} s"}
 
 
+def cpu_model() -> str:
+    """The host CPU's model name, from /proc/cpuinfo where there is one."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_per_config(reps: int = 5) -> dict:
+    """The oracle on one core for each single-frame workload: the median of
+    `reps` timed runs after one warm-up run, next to the GPU's detect time."""
+    import oracle
+    from paper_2003_13493_amd import synth
+    out = {}
+    for name, spec in (("320x240_L1", synth.PLAIN_320), ("752x480_L3", synth.PLAIN_752),
+                       ("1920x1080_L4", synth.PLAIN_1080)):
+        img = spec.make()
+        times = []
+        for i in range(reps + 1):
+            t0 = time.perf_counter()
+            oracle.detect_grid(img, spec.width, spec.levels, spec.t, spec.n, spec.cell)
+            if i:
+                times.append(time.perf_counter() - t0)
+        ms = float(np.median(times)) * 1e3
+        out[name] = {"ms_p50": round(ms, 3), "mpixel_s": round(spec.width * spec.height / ms / 1e3, 3),
+                     "reps": reps}
+    return out
+
+
 def cpu_baseline_parallel(specs, frames, budget_s: float, workers: int) -> dict:
     """The same oracle, frame-parallel: one frame per worker thread (the C
     oracle runs outside the interpreter lock), for about budget_s seconds."""
@@ -469,7 +502,9 @@ def main() -> int:
         out["serving"] = serving(ctx, args.serve_seconds)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(frames0[0], frames0[1], args.cpu_budget)
-        out["cpu_baseline"]["sample"] += f"; host: {os.cpu_count()} logical CPUs"
+        out["cpu_baseline"]["sample"] += f"; host: {os.cpu_count()} logical CPUs, {cpu_model()}"
+        out["cpu_per_config"] = {"workload": "the oracle on one core, one frame, median of 5 runs "
+                                             "after a warm-up", **cpu_per_config()}
         out["cpu_baseline_all_cores"] = cpu_baseline_parallel(frames0[0], frames0[1],
                                                               min(args.cpu_budget, 8.0), args.cpu_workers)
     if args.copy_probe_mib:
