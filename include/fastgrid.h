@@ -180,6 +180,43 @@ int fast_score_maps(fast_ctx *ctx, const fast_plane *pyr, int levels, int t, int
 int fast_nms_grid(fast_ctx *ctx, uint16_t *const *maps, const int32_t *map_pitch, int width,
                   int height, int levels, int radius, int cell, fast_feature *out, void *stream);
 
+/* Lucas-Kanade feature tracking (Section II-E): the pyramidal, approximated
+ * simultaneous inverse compositional tracker with a translational warp
+ * W(x, t) = x + t and affine illumination, q = (tx, ty, alpha, beta).  Each
+ * feature's patch (16x16 on levels 0-1, 8x8 above, at p + (i - S/2, j - S/2))
+ * of the template pyramid `tpl` is aligned to the current pyramid `img`,
+ * coarse to fine; U(x) = [(1+alpha) dT/dx, (1+alpha) dT/dy, T, 1] and the
+ * Hessian sum U U^T are formed once per level at the alpha it starts with,
+ * and each iteration solves H dq = sum U [I(x+t) - (1+alpha) T - beta] and
+ * applies t -= dt, alpha += dalpha, beta += dbeta.  Samples are bilinear,
+ * template gradients central differences.  fp32 on the device.
+ * tpl, img:  `levels` device planes each (as fast_detect_grid), equal sizes.
+ * feats:     device, nfeat x 2 floats: (x, y) in level-0 pixels of tpl.
+ * q:         device, nfeat x 4 floats: in, the initial (tx, ty, alpha, beta)
+ *            with t in level-0 pixels; out, the estimate.
+ * status:    device, nfeat int32: FAST_TRACK_* below.
+ * iters:     device, nfeat int32 iterations over all levels, or NULL.
+ * mode:      FAST_TRACK_GAIN | FAST_TRACK_OFFSET bits select alpha and beta
+ *            (translation is always estimated; unselected ones keep q's).
+ * max_iter:  iterations per level, 0..1000; eps: a level stops once
+ *            |delta t| < eps level pixels (eps >= 0).
+ * A level-k feature sits at (x, y) / 2^k and the level-k translation is
+ * t / 2^k.  A track is lost when a template patch with its 1-pixel gradient
+ * margin does not fit a level, when the warped patch leaves the level, or
+ * when a Cholesky pivot of the Hessian falls to 1e-6 of its diagonal entry.
+ * Errors: FAST_EINVAL for bad planes, mismatched sizes, bad mode, max_iter,
+ * eps or nfeat (< 0 or > 2^24), or NULL arrays with nfeat > 0; FAST_EHIP if
+ * the launch fails.  Asynchronous on `stream`; nfeat = 0 enqueues nothing. */
+#define FAST_TRACK_GAIN 1
+#define FAST_TRACK_OFFSET 2
+#define FAST_TRACK_OK 0
+#define FAST_TRACK_TEMPLATE_OUTSIDE 1
+#define FAST_TRACK_LOST_OUTSIDE 2
+#define FAST_TRACK_SINGULAR 3
+int fast_track(fast_ctx *ctx, const fast_plane *tpl, const fast_plane *img, int levels,
+               const float *feats, float *q, int32_t *status, int32_t *iters, int nfeat, int mode,
+               int max_iter, float eps, void *stream);
+
 /* Batched path: all `njobs` requests (1..FAST_MAX_JOBS, any mix of sizes and
  * parameters) run in one persistent launch fed by a device-side work queue.
  * The job table and its work-item list are enqueued on `stream` as one copy

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 
-HIP_SOURCES = ["fastgrid_kernels.hip", "fastgrid_runtime.hip"]
+HIP_SOURCES = ["fastgrid_kernels.hip", "fasttrack_kernels.hip", "fastgrid_runtime.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

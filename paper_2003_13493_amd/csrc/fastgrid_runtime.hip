@@ -455,6 +455,46 @@ FG_API int fast_nms_grid(fast_ctx *c, uint16_t *const *maps, const int32_t *map_
     return FAST_OK;
 }
 
+FG_API int fast_track(fast_ctx *c, const fast_plane *tpl, const fast_plane *img, int levels, const float *feats,
+                      float *q, int32_t *status, int32_t *iters, int nfeat, int mode, int max_iter, float eps,
+                      void *stream) {
+    if (!c) return FAST_EINVAL;
+    int rc = check_pyr(c, tpl, levels);
+    if (rc) return rc;
+    rc = check_pyr(c, img, levels);
+    if (rc) return rc;
+    if (tpl[0].width != img[0].width || tpl[0].height != img[0].height)
+        return fail(c, FAST_EINVAL, "template and image sizes differ");
+    if (mode & ~(FAST_TRACK_GAIN | FAST_TRACK_OFFSET)) return fail(c, FAST_EINVAL, "unknown mode bits");
+    if (max_iter < 0 || max_iter > 1000) return fail(c, FAST_EINVAL, "max_iter not in 0..1000");
+    if (!(eps >= 0.0f) || eps > 1e30f) return fail(c, FAST_EINVAL, "eps not a finite value >= 0");
+    if (nfeat < 0 || nfeat > (1 << 24)) return fail(c, FAST_EINVAL, "nfeat not in 0..2^24");
+    if (nfeat > 0 && (!feats || !q || !status)) return fail(c, FAST_EINVAL, "feats, q or status is NULL");
+    fg_track_args A;
+    memset(&A, 0, sizeof(A));
+    for (int k = 0; k < levels; ++k) {
+        A.tpl[k] = tpl[k].data;
+        A.img[k] = img[k].data;
+        A.w[k] = tpl[k].width;
+        A.h[k] = tpl[k].height;
+        A.tpitch[k] = tpl[k].pitch;
+        A.ipitch[k] = img[k].pitch;
+    }
+    A.levels = levels;
+    A.feats = feats;
+    A.q = q;
+    A.status = status;
+    A.iters = iters;
+    A.nfeat = nfeat;
+    A.mode = mode;
+    A.max_iter = max_iter;
+    A.eps = eps;
+    DeviceGuard g(c->device);
+    hipError_t e = fg_launch_track(A, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "track launch");
+    return FAST_OK;
+}
+
 FG_API int fast_submit(fast_ctx *c, const fast_job *jobs, int njobs, void *stream, uint64_t *ticket) {
     if (!c) return FAST_EINVAL;
     if (!ticket) return fail(c, FAST_EINVAL, "ticket is NULL");

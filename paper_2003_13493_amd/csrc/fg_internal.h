@@ -39,6 +39,22 @@ size_t fg_smem_bytes(int block);
 // Fill the derived fields of a job (grid, regions) for a launch shape.
 void fg_job_layout(fg_job &j, const fg_launch &L);
 
+// Lucas-Kanade tracking of nfeat features, one wave64 each.
+struct fg_track_args {
+    const uint8_t *tpl[FAST_MAX_LEVELS];
+    const uint8_t *img[FAST_MAX_LEVELS];
+    int32_t w[FAST_MAX_LEVELS], h[FAST_MAX_LEVELS];
+    int32_t tpitch[FAST_MAX_LEVELS], ipitch[FAST_MAX_LEVELS];
+    int32_t levels;
+    const float *feats;   // nfeat x (x, y)
+    float *q;             // nfeat x (tx, ty, alpha, beta), in and out
+    int32_t *status;
+    int32_t *iters;       // or null
+    int32_t nfeat, mode, max_iter;
+    float eps;
+};
+hipError_t fg_launch_track(const fg_track_args &A, hipStream_t s);
+
 // Plain path: one frame.  Enqueues the pyramid (levels 1..L-1) and detection.
 hipError_t fg_launch_plain(const fg_job &j, const fg_launch &L, hipStream_t s);
 

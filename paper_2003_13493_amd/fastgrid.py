@@ -33,7 +33,7 @@ EXPORTS = ("fast_ctx_create", "fast_ctx_destroy", "fast_strerror", "fast_last_er
            "fast_pyr_dims", "fast_grid_dims", "fast_pyr_build", "fast_detect_grid",
            "fast_detect_grid_score", "fast_score_maps", "fast_nms_grid",
            "fast_submit", "fast_poll", "fast_wait", "fast_plan_create", "fast_plan_launch",
-           "fast_plan_destroy", "fast_set_launch")
+           "fast_plan_destroy", "fast_set_launch", "fast_track")
 
 
 class fast_plane(ctypes.Structure):
@@ -89,6 +89,7 @@ def load() -> ctypes.CDLL:
             "fast_score_maps": ([vp, P, i32, i32, i32, i32, ctypes.POINTER(vp), ctypes.POINTER(i32), vp], i32),
             "fast_nms_grid": ([vp, ctypes.POINTER(vp), ctypes.POINTER(i32), i32, i32, i32, i32, i32, vp, vp],
                               i32),
+            "fast_track": ([vp, P, P, i32, vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -247,6 +248,18 @@ def fast_nms_grid(ctx, maps, pitches, width: int, height: int, levels: int, radi
                                      _stream(stream)), "fast_nms_grid")
 
 
+FAST_TRACK_GAIN = 1
+FAST_TRACK_OFFSET = 2
+FAST_TRACK_OK, FAST_TRACK_TEMPLATE_OUTSIDE, FAST_TRACK_LOST_OUTSIDE, FAST_TRACK_SINGULAR = 0, 1, 2, 3
+
+
+def fast_track(ctx, tpl_planes, img_planes, levels: int, feats_ptr: int, q_ptr: int, status_ptr: int,
+               iters_ptr: int, nfeat: int, mode: int, max_iter: int, eps: float, stream=None) -> None:
+    _check(ctx, load().fast_track(ctx, tpl_planes, img_planes, levels, feats_ptr, q_ptr, status_ptr,
+                                  iters_ptr or None, nfeat, mode, max_iter, eps, _stream(stream)),
+           "fast_track")
+
+
 class ScoreMaps:
     """Device score maps of a pyramid: one (H_k, W_k) tensor of uint16 scores per
     level (held as int16), for fast_score_maps / fast_nms_grid."""
@@ -321,6 +334,23 @@ class Context:
     def score_maps(self, pyr: Pyramid, t: int, n: int, maps: ScoreMaps, score: int = FAST_SCORE_SADB,
                    stream=None) -> None:
         fast_score_maps(self.handle, pyr.planes, pyr.levels, t, n, score, maps.ptrs, maps.pitches, stream)
+
+    def track(self, tpl: Pyramid, img: Pyramid, feats, q, status, iters=None,
+              mode: int = FAST_TRACK_GAIN | FAST_TRACK_OFFSET, max_iter: int = 30, eps: float = 0.01,
+              stream=None) -> None:
+        """Lucas-Kanade tracking of feats (device float32, N x 2) from tpl to img;
+        q (device float32, N x 4) holds the initial (tx, ty, alpha, beta) and
+        receives the estimate; status and iters are device int32 of length N."""
+        import torch
+        n = int(feats.shape[0])
+        assert feats.dtype == torch.float32 and feats.is_contiguous() and tuple(feats.shape) == (n, 2)
+        assert q.dtype == torch.float32 and q.is_contiguous() and tuple(q.shape) == (n, 4)
+        assert status.dtype == torch.int32 and status.numel() == n
+        assert iters is None or (iters.dtype == torch.int32 and iters.numel() == n)
+        assert tpl.levels == img.levels
+        fast_track(self.handle, tpl.planes, img.planes, tpl.levels, feats.data_ptr(), q.data_ptr(),
+                   status.data_ptr(), iters.data_ptr() if iters is not None else 0, n, mode, max_iter, eps,
+                   stream)
 
     def nms_grid(self, maps: ScoreMaps, radius: int, cell: int, grid: Grid, stream=None) -> None:
         fast_nms_grid(self.handle, maps.ptrs, maps.pitches, maps.width, maps.height, maps.levels, radius,
