@@ -177,6 +177,87 @@ def nms_radius_sweep(ctx, spec, reps: int = 200) -> dict:
     return out
 
 
+def tracking_bench(ctx, reps: int = 200, with_cpu: bool = True) -> dict:
+    """Lucas-Kanade tracking (Section II-E) timed as Table VI does: 100 tracked
+    features per call, here FAST features detected on a synthetic 752x480
+    frame tracked into a crop of the same scene moved by (3, -2), 3 levels,
+    max 30 iterations per level, eps 0.01, in the four parameter sets; plus
+    1,000 and 10,000 features (seeded uniform positions) to show the scaling.
+    Each call starts from a fresh initial estimate (a separate q per call);
+    microseconds per call from events around `reps` back-to-back calls."""
+    import torch
+    from paper_2003_13493_amd import fastgrid, synth
+    W, H, L = 752, 480, 3
+    scene = synth.frame(W + 16, H + 16, seed=2, nshapes=120, sigma=4.0)
+    tpl = np.ascontiguousarray(scene[8:8 + H, 8:8 + W])
+    img = np.ascontiguousarray(scene[10:10 + H, 5:5 + W])
+    pyrs = []
+    for a in (tpl, img):
+        p = fastgrid.Pyramid(W, H, L)
+        p.upload(a)
+        ctx.pyr_build(p)
+        pyrs.append(p)
+    grid = fastgrid.Grid(W, H, 32)
+    ctx.detect(pyrs[0], 10, 9, 32, grid)
+    slots = grid.fetch()
+    slots = slots[slots["score"] > 0]
+    top = slots[np.argsort(-slots["score"].astype(np.int64), kind="stable")[:100]]
+    f100 = np.stack([top["x"].astype(np.float32) * (1 << top["level"]),
+                     top["y"].astype(np.float32) * (1 << top["level"])], axis=1)
+    rng = np.random.default_rng(77)
+    sets = {"100": f100}
+    for n in (1000, 10000):
+        sets[str(n)] = np.stack([rng.uniform(24, W - 24, n), rng.uniform(24, H - 24, n)], axis=1).astype(np.float32)
+    stream = torch.cuda.current_stream()
+    modes = {"t": 0, "t+offset": fastgrid.FAST_TRACK_OFFSET, "t+gain": fastgrid.FAST_TRACK_GAIN,
+             "t+gain+offset": fastgrid.FAST_TRACK_GAIN | fastgrid.FAST_TRACK_OFFSET}
+    out = {"workload": "Table VI: features tracked per call between two 752x480 frames (the second a crop "
+                       "of the same synthetic scene moved by (3, -2)), 3 levels, 16x16/8x8 patches, max 30 "
+                       "iterations per level, eps 0.01; 100 = the strongest FAST features, 1000/10000 = "
+                       "seeded uniform positions; microseconds per call", "us_per_call": {}}
+    for mname, mode in modes.items():
+        row = {}
+        for key, f in sets.items():
+            n = len(f)
+            feats = torch.tensor(f, device="cuda")
+            r = reps if n <= 1000 else max(20, reps // 5)
+            qs = torch.zeros((r + 5, n, 4), dtype=torch.float32, device="cuda")
+            st = torch.zeros(n, dtype=torch.int32, device="cuda")
+            for i in range(5):
+                ctx.track(pyrs[0], pyrs[1], feats, qs[r + i], st, mode=mode)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for i in range(r):
+                ctx.track(pyrs[0], pyrs[1], feats, qs[i], st, mode=mode)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            row[key] = round(e0.elapsed_time(e1) / r * 1e3, 2)
+            if key == "100":
+                stc = st.cpu().numpy()
+                row["tracked_of_100"] = int((stc == 0).sum())
+                q = qs[0].cpu().numpy()
+                ok = stc == 0
+                row["on_true_motion_of_100"] = int((ok & (np.hypot(q[:, 0] - 3, q[:, 1] + 2) < 0.25)).sum())
+        out["us_per_call"][mname] = row
+    out["paper_table_vi_ms"] = {"workload": "100 features, re-detection at 30; Tegra X2 / i7-6700HQ+960M",
+                                "t": [0.96, 0.33], "t+offset": [0.90, 0.28], "t+gain": [0.91, 0.29],
+                                "t+gain+offset": [1.01, 0.38]}
+    if with_cpu:
+        import oracle
+        from oracle import lk
+        tp = oracle.pyr_build(tpl, W, L)
+        ip = oracle.pyr_build(img, W, L)
+        times = []
+        for i in range(6):
+            t0 = time.perf_counter()
+            lk.track(tp, ip, f100.astype(np.float64), mode=3)
+            if i:
+                times.append(time.perf_counter() - t0)
+        out["cpu_oracle_ms_100_t+gain+offset"] = round(float(np.median(times)) * 1e3, 3)
+    return out
+
+
 def plain_latency(ctx, spec, nframes: int) -> dict:
     """One frame at a time through the plain path with a host sync after each:
     upload from pinned memory, detect, download of the cell slots; stage times
@@ -310,6 +391,8 @@ def main() -> int:
                     help="seconds of Poisson arrivals per serving mode (0 skips serving)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the score-kind and NMS-radius sweeps (profiling runs of the headline kernel)")
+    ap.add_argument("--tracking-only", action="store_true",
+                    help="run only the Lucas-Kanade tracking timings and print them (profiling runs)")
     ap.add_argument("--launch", type=str, default="",
                     help="region,block,blocks_per_cu launch shape (default: library default)")
     args = ap.parse_args()
@@ -328,6 +411,10 @@ def main() -> int:
     if args.launch:
         ctx.set_launch(*[int(v) for v in args.launch.split(",")])
     stream = torch.cuda.current_stream()
+    if args.tracking_only:
+        print(json.dumps({"tracking": tracking_bench(ctx, with_cpu=not args.no_cpu)}))
+        ctx.close()
+        return 0
 
     # resident batch instances
     insts = []
@@ -442,6 +529,8 @@ def main() -> int:
         log(f"plain latency {name}: {latency[name]['upload_detect_download_ms']}")
     nms_sweep = None if args.no_extras else nms_radius_sweep(ctx, synth.PLAIN_752)
     log(f"NMS radius sweep: {nms_sweep}")
+    tracking = None if args.no_extras else tracking_bench(ctx, with_cpu=not args.no_cpu)
+    log(f"tracking: {tracking and tracking['us_per_call']}")
     copy_gbs = copy_bandwidth(1 << 30)
 
     achieved = bytes_per_step / (ms_per_step / 1e3) / 1e9
@@ -482,6 +571,7 @@ def main() -> int:
         "score_kinds_ms_per_step": {"workload": "the same batch with every job scored as SAD-B (the "
                                                 "headline), SAD-A or MT", **kinds_ms},
         "nms_radius_sweep": nms_sweep,
+        "tracking": tracking,
         "step_ms_p50": round(float(np.percentile(step_ms, 50)), 5),
         "step_ms_p99": round(float(np.percentile(step_ms, 99)), 5),
         "plain": {

@@ -64,12 +64,12 @@ def trace(stats_csv: str) -> list[dict]:
                  "total_ns": int(float(r["TotalDurationNs"]))} for r in csv.DictReader(f)]
 
 
-def kernel_source_hash() -> str:
-    """sha256[:16] of the kernel source with comments and blank space removed,
+def kernel_source_hash(name: str = "fastgrid_kernels.hip") -> str:
+    """sha256[:16] of a kernel source with comments and blank space removed,
     so that a record stays valid across comment-only edits."""
     import hashlib
     import re
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "fastgrid_kernels.hip")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", name)
     with open(path) as f:
         text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
@@ -108,8 +108,49 @@ def counters(pmc_dir: str, name_part: str = "detect_batch_kernel") -> dict:
             if per_dispatch(rows, n, name_part)}
 
 
+TRACK_MODES = ("t", "t+offset", "t+gain", "t+gain+offset")
+TRACK_SIZES = ((100, 200), (1000, 200), (10000, 40))   # (features, timed calls) as bench.py runs them
+TRACK_WARMUP = 5
+
+
+def track_md(trace_csv: str, command: str) -> str:
+    """Per-(mode, feature count) averages of the tracking kernel from a kernel
+    trace of ``bench.py --tracking-only``: its dispatches come in the bench's
+    order (for each mode, for each count: warm-up calls, then timed calls)."""
+    durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in _rows(trace_csv)
+            if "track_kernel" in r["Kernel_Name"]]
+    lines = ["# Kernel trace: Lucas-Kanade tracking kernel (one MI355X)", "", "Command (repo root):", "",
+             "    " + command, "",
+             "Summary: `python -m paper_2003_13493_amd.profile_tools track gpurun_out/prof_track/run_kernel_trace.csv`.",
+             "track_kernel is one launch per call, one wave64 per feature; the frames are two 752x480 crops of one",
+             "synthetic scene moved by (3, -2), 3 levels, max 30 iterations per level, eps 0.01.",
+             f"Kernel source hash (sha256[:16] of the source without comments) = {track_source_hash()}.", "",
+             "| parameters | features | calls | average ns | min ns | max ns |", "|---|---|---|---|---|---|"]
+    i = 0
+    for mode in TRACK_MODES:
+        for n, reps in TRACK_SIZES:
+            block = durs[i + TRACK_WARMUP:i + TRACK_WARMUP + reps]
+            i += TRACK_WARMUP + reps
+            if not block:
+                continue
+            lines.append(f"| {mode} | {n} | {len(block)} | {sum(block) // len(block)} | {min(block)} | "
+                         f"{max(block)} |")
+    lines.append("")
+    return "\n".join(lines)
+
+
+def track_source_hash() -> str:
+    return kernel_source_hash("fasttrack_kernels.hip")
+
+
 if __name__ == "__main__":
-    if sys.argv[1] == "trace":
+    if sys.argv[1] == "track":
+        md = track_md(sys.argv[2], sys.argv[4] if len(sys.argv) > 4 else "")
+        if len(sys.argv) > 3:
+            with open(sys.argv[3], "w") as f:
+                f.write(md)
+        print(md)
+    elif sys.argv[1] == "trace":
         if len(sys.argv) > 3:
             with open(sys.argv[3], "w") as f:
                 f.write(trace_md(sys.argv[2], sys.argv[4]))
