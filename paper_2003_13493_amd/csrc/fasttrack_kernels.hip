@@ -9,8 +9,9 @@
 // patch is 4 pixels per lane, an 8x8 patch 1 pixel per lane, so every lane
 // runs the same iterations and exits the same level.  The patch-wide sums
 // (the 10 entries of H once per level, the 4-vector sum of U r per
-// iteration) are butterfly reductions across the wave, then broadcast from
-// lane 0 so every lane takes identical decisions.  Arithmetic is fp32.
+// iteration) are DPP reductions across each row of 16 lanes whose four row
+// sums every lane then reads in the same order, so every lane holds the same
+// value and takes identical decisions.  Arithmetic is fp32.
 //
 // Every sample of a patch sits at p + t + (integer offset), so all of them
 // share one fractional part: positions are split into an integer base and a
@@ -24,10 +25,27 @@ namespace {
 
 constexpr int TRACK_WAVES = 4;   // features per workgroup
 
+// v plus its DPP-permuted copy (a register move, no LDS traffic)
+template <int CTRL>
+__device__ __forceinline__ float dpp_add(float v) {
+    const int p = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false);
+    return v + __builtin_bit_cast(float, p);
+}
+
+// Sum over the wave, the same value in every lane: within each row of 16
+// lanes by swapping neighbours (quad_perm 1,0,3,2 and 2,3,0,1), halves of 8
+// (row_half_mirror) and halves of the row (row_mirror), then the four row
+// sums read out in a fixed order.
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+    v = dpp_add<0xB1>(v);
+    v = dpp_add<0x4E>(v);
+    v = dpp_add<0x141>(v);
+    v = dpp_add<0x140>(v);
+    const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
+    const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+    const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+    const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+    return (r0 + r1) + (r2 + r3);
 }
 
 __device__ __forceinline__ float uniform(float v) {
@@ -109,8 +127,10 @@ __device__ void track_level(const fg_track_args &A, int k, float pxf, int pxi, f
     M[3][1] = offset ? wave_sum(h13) : 0.0f;
     M[3][2] = gain && offset ? wave_sum(h23) : 0.0f;
     M[3][3] = offset ? wave_sum(h33) : 1.0f;
-    // Cholesky factor; singular when a pivot falls to 1e-6 of its diagonal
-    float L[4][4] = {};
+    // Cholesky factor, with the reciprocals of its diagonal kept so the
+    // per-iteration solve has no divisions; singular when a pivot falls to
+    // 1e-6 of its diagonal entry
+    float L[4][4] = {}, inv[4];
     bool singular = false;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -122,8 +142,9 @@ __device__ void track_level(const fg_track_args &A, int k, float pxf, int pxi, f
             if (i == j) {
                 singular |= !(s > 1e-6f * M[i][i]);
                 L[i][i] = sqrtf(fmaxf(s, 0.0f));
+                inv[i] = L[i][i] > 0.0f ? 1.0f / L[i][i] : 0.0f;
             } else {
-                L[i][j] = L[j][j] > 0.0f ? s / L[j][j] : 0.0f;
+                L[i][j] = s * inv[j];
             }
         }
     }
@@ -162,14 +183,14 @@ __device__ void track_level(const fg_track_args &A, int k, float pxf, int pxi, f
             float s = rhs[i];
 #pragma unroll
             for (int q = 0; q < i; ++q) s -= L[i][q] * y[q];
-            y[i] = s / L[i][i];
+            y[i] = s * inv[i];
         }
 #pragma unroll
         for (int i = 3; i >= 0; --i) {
             float s = y[i];
 #pragma unroll
             for (int q = i + 1; q < 4; ++q) s -= L[q][i] * d[q];
-            d[i] = s / L[i][i];
+            d[i] = s * inv[i];
         }
         ++total;
         tkx = uniform(tkx - d[0]);
