@@ -258,6 +258,35 @@ def tracking_bench(ctx, reps: int = 200, with_cpu: bool = True) -> dict:
     return out
 
 
+def frontend_bench(ctx, nframes: int = 300) -> dict:
+    """The detect-and-track loop (re-detection below 30% of 100 target tracks)
+    over a moving 752x480 sequence: crops of one synthetic scene following a
+    seeded random walk of up to 3 pixels per frame.  Per frame: upload from
+    host memory, pyramid, tracking of the live features, the host's keep/drop
+    decisions and, when needed, detection; wall time per frame with the
+    syncs it needs."""
+    from paper_2003_13493_amd import frontend, synth
+    W, H = 752, 480
+    scene = synth.frame(W + 64, H + 64, seed=2, nshapes=150, sigma=4.0)[:, :W + 64]
+    rng = np.random.default_rng(5)
+    o = np.array([32, 32])
+    frames = []
+    for _ in range(nframes):
+        o = np.clip(o + rng.integers(-3, 4, size=2), 0, 64)
+        frames.append(np.ascontiguousarray(scene[o[1]:o[1] + H, o[0]:o[0] + W]))
+    fe = frontend.Frontend(ctx, W, H, 3, 10, 9, 32, target=100)
+    for img in frames[:10]:
+        fe.step(img)
+    fe = frontend.Frontend(ctx, W, H, 3, 10, 9, 32, target=100)
+    recs = [fe.step(img) for img in frames]
+    ms = np.array([r["ms"] for r in recs])
+    return {"workload": f"{nframes} frames of 752x480, 3 levels, 100 target tracks, re-detection below 30%, "
+                        "translation + gain + offset; host wall time per frame including the upload",
+            "ms_p50": round(float(np.percentile(ms, 50)), 4), "ms_p99": round(float(np.percentile(ms, 99)), 4),
+            "redetections": int(sum(r["redetect"] for r in recs)),
+            "mean_live_tracks": round(float(np.mean([r["live"] for r in recs])), 1)}
+
+
 def plain_latency(ctx, spec, nframes: int) -> dict:
     """One frame at a time through the plain path with a host sync after each:
     upload from pinned memory, detect, download of the cell slots; stage times
@@ -412,7 +441,8 @@ def main() -> int:
         ctx.set_launch(*[int(v) for v in args.launch.split(",")])
     stream = torch.cuda.current_stream()
     if args.tracking_only:
-        print(json.dumps({"tracking": tracking_bench(ctx, with_cpu=not args.no_cpu)}))
+        print(json.dumps({"tracking": tracking_bench(ctx, with_cpu=not args.no_cpu),
+                          "frontend": frontend_bench(ctx)}))
         ctx.close()
         return 0
 
@@ -531,6 +561,8 @@ def main() -> int:
     log(f"NMS radius sweep: {nms_sweep}")
     tracking = None if args.no_extras else tracking_bench(ctx, with_cpu=not args.no_cpu)
     log(f"tracking: {tracking and tracking['us_per_call']}")
+    front = None if args.no_extras else frontend_bench(ctx)
+    log(f"frontend: {front}")
     copy_gbs = copy_bandwidth(1 << 30)
 
     achieved = bytes_per_step / (ms_per_step / 1e3) / 1e9
@@ -572,6 +604,7 @@ def main() -> int:
                                                 "headline), SAD-A or MT", **kinds_ms},
         "nms_radius_sweep": nms_sweep,
         "tracking": tracking,
+        "frontend": front,
         "step_ms_p50": round(float(np.percentile(step_ms, 50)), 5),
         "step_ms_p99": round(float(np.percentile(step_ms, 99)), 5),
         "plain": {

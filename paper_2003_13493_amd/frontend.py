@@ -1,0 +1,100 @@
+"""Detect-and-track front end of one camera: the paper's tracking workload
+(Section IV, feature tracker evaluation).  FAST features (one per grid cell)
+are tracked frame to frame by the Lucas-Kanade tracker, and detection runs
+again whenever the number of live tracks falls below a fraction (30%) of the
+target count.
+
+Every frame: upload into one of two device pyramids, build its levels,
+track the live features from the previous frame's pyramid, drop the lost
+ones, and if fewer than ``redetect_frac * target`` remain, detect on the new
+frame and add the strongest cell winners whose cells hold no live track
+(strongest first; equal scores by cell index) up to the target.  All image
+work runs in the HIP library; the host keeps the short feature list.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import fastgrid
+
+
+def cell_of(xy: np.ndarray, cell: int, gw: int) -> np.ndarray:
+    """Row-major grid cell index of level-0 positions."""
+    cx = np.floor(xy[:, 0] / cell).astype(np.int64)
+    cy = np.floor(xy[:, 1] / cell).astype(np.int64)
+    return cy * gw + cx
+
+
+def pick_new(slots: np.ndarray, taken: np.ndarray, count: int) -> np.ndarray:
+    """The `count` strongest cell winners outside the `taken` cells, as level-0
+    (x, y); equal scores keep the lower cell index first."""
+    flat = slots.reshape(-1)
+    free = (flat["score"] > 0) & ~taken
+    idx = np.nonzero(free)[0]
+    order = np.lexsort((idx, -flat["score"][idx].astype(np.int64)))
+    idx = idx[order][:max(count, 0)]
+    lv = flat["level"][idx].astype(np.int64)
+    return np.stack([(flat["x"][idx].astype(np.int64) << lv).astype(np.float64),
+                     (flat["y"][idx].astype(np.int64) << lv).astype(np.float64)], axis=1)
+
+
+class Frontend:
+    def __init__(self, ctx: fastgrid.Context, width: int, height: int, levels: int = 3, t: int = 10,
+                 n: int = 9, cell: int = 32, target: int = 100, redetect_frac: float = 0.3,
+                 mode: int = fastgrid.FAST_TRACK_GAIN | fastgrid.FAST_TRACK_OFFSET, max_iter: int = 30,
+                 eps: float = 0.01):
+        import torch
+        self.ctx, self.w, self.h, self.levels = ctx, width, height, levels
+        self.t, self.n, self.cell = t, n, cell
+        self.target, self.redetect_frac = target, redetect_frac
+        self.mode, self.max_iter, self.eps = mode, max_iter, eps
+        self.pyr = [fastgrid.Pyramid(width, height, levels) for _ in range(2)]
+        self.grid = fastgrid.Grid(width, height, cell)
+        self.gw = (width + cell - 1) // cell
+        self.gh = (height + cell - 1) // cell
+        self.cur = 0
+        self.frames = 0
+        self.feats = np.zeros((0, 2))     # live features, level-0 positions in the current frame
+        self.last_q = np.zeros((0, 4))    # the last tracking call's estimates and statuses
+        self.last_status = np.zeros(0, dtype=np.int32)
+        self.f_dev = torch.zeros((target, 2), dtype=torch.float32, device="cuda")
+        self.q_dev = torch.zeros((target, 4), dtype=torch.float32, device="cuda")
+        self.s_dev = torch.zeros(target, dtype=torch.int32, device="cuda")
+
+    def step(self, frame: np.ndarray) -> dict:
+        """Process one frame (host uint8, height x >= width); returns what
+        happened: live tracks before and after, whether detection ran."""
+        import torch
+        t0 = time.perf_counter()
+        prev, cur = self.pyr[self.cur], self.pyr[1 - self.cur]
+        cur.upload(frame)
+        self.ctx.pyr_build(cur)
+        tracked = 0
+        if self.frames > 0 and len(self.feats):
+            k = len(self.feats)
+            self.f_dev[:k].copy_(torch.from_numpy(self.feats.astype(np.float32)))
+            self.q_dev[:k].zero_()
+            self.ctx.track(prev, cur, self.f_dev[:k], self.q_dev[:k], self.s_dev[:k], mode=self.mode,
+                           max_iter=self.max_iter, eps=self.eps)
+            q = self.q_dev[:k].cpu().numpy().astype(np.float64)
+            st = self.s_dev[:k].cpu().numpy()
+            keep = st == fastgrid.FAST_TRACK_OK
+            self.last_q, self.last_status = q, st
+            self.feats = self.feats[keep] + q[keep, :2]
+            tracked = int(keep.sum())
+        redetect = len(self.feats) < self.redetect_frac * self.target
+        if redetect:
+            self.ctx.detect(cur, self.t, self.n, self.cell, self.grid)
+            slots = self.grid.fetch()
+            taken = np.zeros(self.gw * self.gh, dtype=bool)
+            if len(self.feats):
+                c = cell_of(self.feats, self.cell, self.gw)
+                taken[c[(c >= 0) & (c < len(taken))]] = True
+            new = pick_new(slots, taken, self.target - len(self.feats))
+            self.feats = np.concatenate([self.feats, new]) if len(self.feats) else new
+        self.cur = 1 - self.cur
+        self.frames += 1
+        return {"tracked": tracked, "redetect": bool(redetect), "live": len(self.feats),
+                "ms": (time.perf_counter() - t0) * 1e3}
