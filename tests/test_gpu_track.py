@@ -198,3 +198,38 @@ def test_track_rejects_bad_arguments(ctx):
     # nothing to track is not an error
     fastgrid.fast_track(ctx.handle, tp.planes, ip.planes, 2, 0, 0, 0, 0, 0, 3, 10, 0.01)
     assert ctypes.sizeof(fastgrid.fast_plane) == 24
+
+
+@pytest.mark.parametrize("levels", [1, 2, 5])
+def test_track_pyramid_depths(ctx, levels):
+    """One level (16x16 patches only), two, and five (three 8x8 levels) on a
+    1280x720 pair, with a motion each depth can reach."""
+    print(f"case track depth {levels}", flush=True)
+    d = {1: (1.25, -0.75), 2: (3.5, 2.25), 5: (-9.0, 7.5)}[levels]
+    wl = (14.0, 40.0) if levels < 5 else (40.0, 90.0)
+    tpl = wave_frame(1280, 720, seed=70 + levels, wavelengths=wl)
+    margin = 12 << (levels - 1) if levels > 1 else 12
+    feats = feature_grid(1280, 720, min(margin, 200), 53) + np.array([0.5, 0.25])
+    for mode in (0, 3):
+        # the full model also sees an illumination change
+        gain, off = (1.05, -3.0) if mode else (1.0, 0.0)
+        img = wave_frame(1280, 720, seed=70 + levels, d=d, gain=gain, offset=off, wavelengths=wl)
+        got = gpu_track(ctx, tpl, img, levels, feats, mode=mode, eps=1e-3)
+        want = cpu_track(tpl, img, levels, feats, mode=mode, eps=1e-3)
+        near = np.hypot(want[0][:, 0] - d[0], want[0][:, 1] - d[1]) < 0.5
+        ok = compare(got, want, 1e-3, f"depth {levels} mode {mode}", where=near)
+        assert ok.sum() > len(feats) // 2
+
+
+def test_track_4k_frame(ctx):
+    """Features across a 4096x2160, 5-level pair (the largest stream frame)."""
+    print("case track 4k", flush=True)
+    tpl = wave_frame(4096, 2160, seed=80, wavelengths=(30.0, 80.0))
+    img = wave_frame(4096, 2160, seed=80, d=(6.5, -4.25), wavelengths=(30.0, 80.0))
+    rng = np.random.default_rng(80)
+    feats = np.stack([rng.uniform(0, 4096, 400), rng.uniform(0, 2160, 400)], axis=1)
+    got = gpu_track(ctx, tpl, img, 5, feats, mode=3, eps=1e-3)
+    want = cpu_track(tpl, img, 5, feats, mode=3, eps=1e-3)
+    near = np.hypot(want[0][:, 0] - 6.5, want[0][:, 1] + 4.25) < 0.5
+    ok = compare(got, want, 1e-3, "4k", where=near)
+    assert ok.sum() > 250
