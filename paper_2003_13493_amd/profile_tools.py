@@ -121,7 +121,7 @@ def track_md(trace_csv: str, command: str) -> str:
             if "track_kernel" in r["Kernel_Name"]]
     lines = ["# Kernel trace: Lucas-Kanade tracking kernel (one MI355X)", "", "Command (repo root):", "",
              "    " + command, "",
-             "Summary: `python -m paper_2003_13493_amd.profile_tools track gpurun_out/prof_track/run_kernel_trace.csv`.",
+             f"Summary: `python -m paper_2003_13493_amd.profile_tools track {trace_csv}`.",
              "track_kernel is one launch per call, one wave64 per feature; the frames are two 752x480 crops of one",
              "synthetic scene moved by (3, -2), 3 levels, max 30 iterations per level, eps 0.01.",
              f"Kernel source hash (sha256[:16] of the source without comments) = {track_source_hash()}.", "",
