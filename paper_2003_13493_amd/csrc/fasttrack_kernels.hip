@@ -202,7 +202,9 @@ __device__ void track_level(const fg_track_args &A, int k, float pxf, int pxi, f
 }
 
 __global__ void __launch_bounds__(64 * TRACK_WAVES) track_kernel(fg_track_args A) {
-    const int f = blockIdx.x * TRACK_WAVES + (int)(threadIdx.x >> 6);
+    // the wave's feature, provably uniform: its loads become scalar loads and
+    // the tests and loops on its position become scalar branches
+    const int f = __builtin_amdgcn_readfirstlane(blockIdx.x * TRACK_WAVES + (int)(threadIdx.x >> 6));
     if (f >= A.nfeat) return;   // whole waves leave together
     const float fx = A.feats[2 * f], fy = A.feats[2 * f + 1];
     float tx = A.q[4 * f], ty = A.q[4 * f + 1], alpha = A.q[4 * f + 2], beta = A.q[4 * f + 3];
