@@ -204,9 +204,11 @@ int fast_nms_grid(fast_ctx *ctx, uint16_t *const *maps, const int32_t *map_pitch
  * t / 2^k.  A track is lost when a template patch with its 1-pixel gradient
  * margin does not fit a level, when the warped patch leaves the level, or
  * when a Cholesky pivot of the Hessian falls to 1e-6 of its diagonal entry.
+ * feats, q, status and iters must be 4-byte aligned.
  * Errors: FAST_EINVAL for bad planes, mismatched sizes, bad mode, max_iter,
- * eps or nfeat (< 0 or > 2^24), or NULL arrays with nfeat > 0; FAST_EHIP if
- * the launch fails.  Asynchronous on `stream`; nfeat = 0 enqueues nothing. */
+ * eps or nfeat (< 0 or > 2^24), NULL arrays with nfeat > 0, or misaligned
+ * arrays; FAST_EHIP if the launch fails.  Asynchronous on `stream`; nfeat = 0
+ * enqueues nothing. */
 #define FAST_TRACK_GAIN 1
 #define FAST_TRACK_OFFSET 2
 #define FAST_TRACK_OK 0

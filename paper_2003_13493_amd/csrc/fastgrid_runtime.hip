@@ -470,6 +470,8 @@ FG_API int fast_track(fast_ctx *c, const fast_plane *tpl, const fast_plane *img,
     if (!(eps >= 0.0f) || eps > 1e30f) return fail(c, FAST_EINVAL, "eps not a finite value >= 0");
     if (nfeat < 0 || nfeat > (1 << 24)) return fail(c, FAST_EINVAL, "nfeat not in 0..2^24");
     if (nfeat > 0 && (!feats || !q || !status)) return fail(c, FAST_EINVAL, "feats, q or status is NULL");
+    if ((((uintptr_t)feats | (uintptr_t)q | (uintptr_t)status | (uintptr_t)iters) & 3u) != 0)
+        return fail(c, FAST_EINVAL, "feats, q, status or iters not 4-byte aligned");
     fg_track_args A;
     memset(&A, 0, sizeof(A));
     for (int k = 0; k < levels; ++k) {

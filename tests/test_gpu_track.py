@@ -195,6 +195,10 @@ def test_track_rejects_bad_arguments(ctx):
     with pytest.raises(fastgrid.FastError) as ei:
         fastgrid.fast_track(ctx.handle, tp.planes, ip.planes, 2, f.data_ptr(), 0, st.data_ptr(), 0, 4, 3, 10, 0.01)
     assert ei.value.code == fastgrid.FAST_EINVAL
+    with pytest.raises(fastgrid.FastError) as ei:   # misaligned estimates
+        fastgrid.fast_track(ctx.handle, tp.planes, ip.planes, 2, f.data_ptr(), q.data_ptr() + 2, st.data_ptr(), 0,
+                            4, 3, 10, 0.01)
+    assert ei.value.code == fastgrid.FAST_EINVAL
     # nothing to track is not an error
     fastgrid.fast_track(ctx.handle, tp.planes, ip.planes, 2, 0, 0, 0, 0, 0, 3, 10, 0.01)
     assert ctypes.sizeof(fastgrid.fast_plane) == 24
