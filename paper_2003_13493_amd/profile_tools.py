@@ -139,12 +139,60 @@ def track_md(trace_csv: str, command: str) -> str:
     return "\n".join(lines)
 
 
+def track_counters_md(pmc_dir: str, command: str) -> str:
+    """Per-(mode, feature count) medians of SQ counters of the tracking kernel,
+    per wave, from a ``--pmc`` run of ``bench.py --tracking-only`` (dispatches
+    in the bench's order, as for track_md)."""
+    rows = [r for r in _rows(pmc_dir) if "track_kernel" in r["Kernel_Name"]]
+    order, per = [], {}
+    for r in rows:
+        d = int(r["Dispatch_Id"])
+        if d not in per:
+            per[d] = {}
+            order.append(d)
+        per[d][r["Counter_Name"]] = per[d].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    order.sort()
+    lines = ["# SQ counters: Lucas-Kanade tracking kernel (one MI355X)", "", "Command (repo root):", "",
+             "    " + command, "",
+             f"Summary: `python -m paper_2003_13493_amd.profile_tools track-counters {pmc_dir}`.",
+             "Medians over each configuration's timed dispatches, per wave (one wave is one feature).",
+             "wait = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES; VALU active = SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES.",
+             f"Kernel source hash (sha256[:16] of the source without comments) = {track_source_hash()}.", "",
+             "| parameters | features | VALU instr / wave | SALU instr / wave | VMEM instr / wave | "
+             "wave cycles / wave | wait | VALU active |", "|---|---|---|---|---|---|---|---|"]
+    i = 0
+    for mode in TRACK_MODES:
+        for n, reps in TRACK_SIZES:
+            block = [per[d] for d in order[i + TRACK_WARMUP:i + TRACK_WARMUP + reps]]
+            i += TRACK_WARMUP + reps
+            if not block:
+                continue
+
+            def med(key):
+                vals = [b.get(key, 0.0) / max(b.get("SQ_WAVES", 1.0), 1.0) for b in block]
+                return statistics.median(vals)
+
+            cyc = med("SQ_WAVE_CYCLES")
+            lines.append(f"| {mode} | {n} | {med('SQ_INSTS_VALU'):.0f} | {med('SQ_INSTS_SALU'):.0f} | "
+                         f"{med('SQ_INSTS_VMEM'):.0f} | {cyc:.0f} | "
+                         f"{med('SQ_WAIT_INST_ANY') / cyc if cyc else 0:.2f} | "
+                         f"{med('SQ_ACTIVE_INST_VALU') / cyc if cyc else 0:.2f} |")
+    lines.append("")
+    return "\n".join(lines)
+
+
 def track_source_hash() -> str:
     return kernel_source_hash("fasttrack_kernels.hip")
 
 
 if __name__ == "__main__":
-    if sys.argv[1] == "track":
+    if sys.argv[1] == "track-counters":
+        md = track_counters_md(sys.argv[2], sys.argv[4] if len(sys.argv) > 4 else "")
+        if len(sys.argv) > 3:
+            with open(sys.argv[3], "w") as f:
+                f.write(md)
+        print(md)
+    elif sys.argv[1] == "track":
         md = track_md(sys.argv[2], sys.argv[4] if len(sys.argv) > 4 else "")
         if len(sys.argv) > 3:
             with open(sys.argv[3], "w") as f:
