@@ -237,3 +237,26 @@ def test_track_4k_frame(ctx):
     near = np.hypot(want[0][:, 0] - 6.5, want[0][:, 1] + 4.25) < 0.5
     ok = compare(got, want, 1e-3, "4k", where=near)
     assert ok.sum() > 250
+
+
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_track_fixed_step_count_matches_tightly(ctx, mode):
+    """With eps = 0 no level stops early: both sides take exactly max_iter
+    Gauss-Newton steps per level, so iteration counts agree exactly and the
+    estimates differ only by fp32 rounding."""
+    print(f"case track fixed steps mode {mode}", flush=True)
+    tpl = wave_frame(W, H, seed=90)
+    img = wave_frame(W, H, seed=90, d=(1.75, -2.5), gain=1.1 if mode else 1.0, offset=-6.0 if mode else 0.0)
+    feats = feature_grid(W, H, 30, 23) + np.array([0.375, 0.625])
+    got = gpu_track(ctx, tpl, img, 3, feats, mode=mode, max_iter=6, eps=0.0)
+    want = cpu_track(tpl, img, 3, feats, mode=mode, max_iter=6, eps=0.0)
+    assert (got[1] == want[1]).all()
+    ok = want[1] == lk.TRACKED
+    assert ok.sum() > len(feats) // 2
+    assert (got[2][ok] == 18).all() and (want[2][ok] == 18).all()
+    near = np.hypot(want[0][:, 0] - 1.75, want[0][:, 1] + 2.5) < 0.5
+    sel = ok & near
+    assert sel.sum() > len(feats) // 2
+    assert np.abs(got[0][sel, :2] - want[0][sel, :2]).max() < 2e-3
+    assert np.abs(got[0][sel, 2] - want[0][sel, 2]).max() < 1e-3
+    assert np.abs(got[0][sel, 3] - want[0][sel, 3]).max() < 0.1
