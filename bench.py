@@ -41,22 +41,39 @@ def algorithmic_bytes(specs) -> int:
     return total
 
 
-def cpu_baseline(specs, frames, budget_s: float) -> dict:
+def cpu_baseline(specs, frames, budget_s: float, gpu=None) -> dict:
     """The CPU oracle, single-threaded, cycling over the batch's frames until
-    about budget_s seconds of work (a bounded sample of the same workload)."""
+    about budget_s seconds of work (a bounded sample of the same workload),
+    and at least once over every frame.  `gpu` holds, per frame, the slots and
+    the pyramid levels 1.. that the timed launches left on the device; each is
+    compared bit for bit with the oracle's answer for that frame (outside any
+    timed region), which gives the line's parity flag."""
     import oracle
     done_px, t_total, nframes = 0, 0.0, 0
-    while t_total < budget_s:
+    mismatched = []
+    while t_total < budget_s or nframes < len(specs):
         s, img = specs[nframes % len(specs)], frames[nframes % len(frames)]
         t0 = time.perf_counter()
-        oracle.detect_grid(img, s.width, s.levels, s.t, s.n, s.cell)
+        slots, planes = oracle.detect_grid(img, s.width, s.levels, s.t, s.n, s.cell)
         t_total += time.perf_counter() - t0
+        if gpu is not None and nframes < len(specs):
+            g_slots, g_levels = gpu[nframes]
+            same = np.array_equal(g_slots, slots) and all(
+                np.array_equal(g_levels[k - 1], planes[k][0][:, :planes[k][1]]) for k in range(1, s.levels))
+            if not same:
+                mismatched.append(nframes)
         done_px += s.width * s.height
         nframes += 1
-    return {"value": round(done_px / t_total / 1e6, 3), "unit": "Mpixel/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{nframes} frames of the 64-frame batch in order, single-threaded, "
-                      f"{t_total:.1f} s"}
+    out = {"value": round(done_px / t_total / 1e6, 3), "unit": "Mpixel/s", "cores": 1,
+           "kind": "oracle",
+           "sample": f"{nframes} frames of the 64-frame batch in order, single-threaded, "
+                     f"{t_total:.1f} s"}
+    if gpu is not None:
+        out["parity"] = {"equal": not mismatched, "frames_compared": len(specs),
+                         "mismatched_frames": mismatched[:8],
+                         "what": "slots and pyramid levels 1.. of every frame of resident instance 0 as the "
+                                 "timed launches left them, against the oracle, bit for bit"}
+    return out
 
 
 def cpu_model() -> str:
@@ -496,6 +513,10 @@ def main() -> int:
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(nd)])
+    # what the timed launches left in instance 0 (checked against the oracle
+    # by the CPU-baseline leg; later sections rewrite these outputs)
+    gpu_out0 = [(g.fetch().copy(), [p.level(k) for k in range(1, s.levels)])
+                for s, p, g in zip(insts[0][0], insts[0][1], insts[0][2])]
 
     # the same resident batches replayed as captured HIP graphs
     gplans = [ctx.plan_create(inst[3], graph=True) for inst in insts]
@@ -619,12 +640,14 @@ def main() -> int:
             **latency,
         },
         "wall_s_timed": round(t_wall, 3),
+        "parity": None,
     }
     log(f"plain: {plain_ms:.4f} ms per 64 frames")
     if args.serve_seconds > 0:
         out["serving"] = serving(ctx, args.serve_seconds)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(frames0[0], frames0[1], args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(frames0[0], frames0[1], args.cpu_budget, gpu=gpu_out0)
+        out["parity"] = out["cpu_baseline"]["parity"]["equal"]
         out["cpu_baseline"]["sample"] += f"; host: {os.cpu_count()} logical CPUs, {cpu_model()}"
         out["cpu_per_config"] = {"workload": "the oracle on one core, one frame, median of 5 runs "
                                              "after a warm-up", **cpu_per_config()}

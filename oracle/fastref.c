@@ -25,8 +25,8 @@ static int px(const fastref_plane *p, int x, int y) {
     return p->data[(size_t)y * (size_t)p->pitch + (size_t)x];
 }
 
-/* Pyramid (Section II-B "the input image is first subsampled"; Section III-C
- * "each subsequent layer halves the resolution of the previous one").
+/* Pyramid (Section II-B: the detector first builds subsampled copies of the
+ * input; Section III-C: every level has half the resolution of the one below).
  * READING: the halving filter is the rounded 2x2 mean (a+b+c+d+2)>>2 applied to
  * the previous level (not to level 0 directly); odd trailing rows/columns are
  * dropped (floor). */
@@ -77,7 +77,7 @@ int fastref_arc(uint32_t mask16, int n) {
  * two labels does not count); pixels closer than 3 to any image edge are not
  * tested (score 0); the score is the whole-circle thresholded sum of the
  * winning side, max(sum_bright (p - c - t), sum_dark (c - p - t)), and 0 when
- * the test fails (the paper: "The corner score is 0 if the segment test fails"). */
+ * the test fails (Section II-D gives every score kind the value 0 there). */
 static int outside_test_area(const fastref_plane *img, int x, int y) {
     return x < 3 || y < 3 || x > img->width - 4 || y > img->height - 4;
 }

@@ -1,8 +1,9 @@
 """Detect-and-track front end of one camera: the paper's tracking workload
-(Section IV, feature tracker evaluation).  FAST features (one per grid cell)
-are tracked frame to frame by the Lucas-Kanade tracker, and detection runs
-again whenever the number of live tracks falls below a fraction (30%) of the
-target count.
+(Section III-D, the feature tracker evaluation).  FAST features (one per grid
+cell) are tracked frame to frame by the Lucas-Kanade tracker, and detection
+runs again whenever the number of live tracks falls below a fraction (30%) of
+the target count.  Detection uses the second of the three corner scores that
+Section II-D lists, the arc sum SAD-A, as the evaluation does.
 
 Every frame: upload into one of two device pyramids, build its levels,
 track the live features from the previous frame's pyramid, drop the lost
@@ -44,12 +45,13 @@ class Frontend:
     def __init__(self, ctx: fastgrid.Context, width: int, height: int, levels: int = 3, t: int = 10,
                  n: int = 9, cell: int = 32, target: int = 100, redetect_frac: float = 0.3,
                  mode: int = fastgrid.FAST_TRACK_GAIN | fastgrid.FAST_TRACK_OFFSET, max_iter: int = 30,
-                 eps: float = 0.01):
+                 eps: float = 0.01, score: int = fastgrid.FAST_SCORE_SADA):
         import torch
         self.ctx, self.w, self.h, self.levels = ctx, width, height, levels
         self.t, self.n, self.cell = t, n, cell
         self.target, self.redetect_frac = target, redetect_frac
         self.mode, self.max_iter, self.eps = mode, max_iter, eps
+        self.score = score
         self.pyr = [fastgrid.Pyramid(width, height, levels) for _ in range(2)]
         self.grid = fastgrid.Grid(width, height, cell)
         self.gw = (width + cell - 1) // cell
@@ -86,7 +88,7 @@ class Frontend:
             tracked = int(keep.sum())
         redetect = len(self.feats) < self.redetect_frac * self.target
         if redetect:
-            self.ctx.detect(cur, self.t, self.n, self.cell, self.grid)
+            self.ctx.detect(cur, self.t, self.n, self.cell, self.grid, score=self.score)
             slots = self.grid.fetch()
             taken = np.zeros(self.gw * self.gh, dtype=bool)
             if len(self.feats):

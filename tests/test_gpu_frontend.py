@@ -57,7 +57,8 @@ def oracle_loop(frames, target, frac, mode, eps):
             tracked = int(keep.sum())
         redetect = len(feats) < frac * target
         if redetect:
-            slots, _ = oracle.detect_grid(img, W, LEVELS, T, N, CELL)
+            # Section III-D detects with score (ii) of Section II-D's list: SAD-A
+            slots, _ = oracle.detect_grid(img, W, LEVELS, T, N, CELL, kind=oracle.SCORE_SADA)
             flat = slots.reshape(-1)
             busy = set()
             for x, y in feats:

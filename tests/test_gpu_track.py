@@ -3,7 +3,9 @@ against the fp64 CPU oracle.  The kernel computes in fp32, so parameters agree
 within a tolerance and statuses exactly.  A level stops once its step is under
 eps, so the two sides may stop one iteration apart, and the last step moves t
 by less than eps.  The translation tolerance is therefore 2 eps plus fp32
-rounding; gain and offset get the matching bounds."""
+rounding; gain and offset get the matching bounds.  Parameters are compared on
+every tracked feature, except on the noisy detected-corner frames, where the
+compared tracks are chosen from the template alone (tests/wellposed.py)."""
 import ctypes
 
 import numpy as np
@@ -12,6 +14,7 @@ import pytest
 import oracle
 from oracle import lk
 from lkdata import feature_grid, wave_frame
+from wellposed import min_eig_per_level
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -73,6 +76,7 @@ def compare(got, want, eps, tag, t_tol=None, where=None):
     dt = np.abs(qg[ok, :2] - qw[ok, :2]).max(initial=0)
     da = np.abs(qg[ok, 2] - qw[ok, 2]).max(initial=0)
     db = np.abs(qg[ok, 3] - qw[ok, 3]).max(initial=0)
+    print(f"{tag}: {int(ok.sum())} compared, max |dt| {dt:.2e}, |dalpha| {da:.2e}, |dbeta| {db:.2e}", flush=True)
     assert dt <= t_tol, f"{tag}: translation differs by {dt}"
     assert da <= 2e-3 + 4 * eps * 0.05, f"{tag}: gain differs by {da}"
     assert db <= 0.25 + 4 * eps * 8, f"{tag}: offset differs by {db}"
@@ -104,10 +108,13 @@ def test_track_detected_features_on_moving_frames(ctx, mode):
     752x480 frame, tracked into the next frame, a crop of the same scene moved
     by a few pixels with fresh noise.  Some corners of this scene sit on long
     straight edges, where the alignment is ill-posed along the edge: such a
-    track wanders, and fp32 and fp64 rounding send it to different places.
-    Parameters are therefore compared where the oracle recovers the true
-    motion (a unique answer), statuses everywhere, and the sets of tracks that
-    recover the motion must agree."""
+    track can slide, and fp32 and fp64 rounding may send it to different
+    places.  The tracks compared are chosen from the template alone: every
+    level's patch has a translational Hessian block whose smaller eigenvalue
+    is at least 16 (intensity^2 per pixel^2, patch mean), eight times the
+    gradient variance of the sigma = 2 noise.  On those, parameters must agree
+    within the tracker tolerance; statuses must agree everywhere, and the sets
+    of tracks that recover the true motion may differ in a few ill-posed ones."""
     print(f"case track detected mode {mode}", flush=True)
     scene = synth.frame(752 + 16, 480 + 16, seed=31, nshapes=120, sigma=0.0)
     rng = np.random.default_rng(31)
@@ -121,12 +128,15 @@ def test_track_detected_features_on_moving_frames(ctx, mode):
     feats = np.stack([slots["x"][sel].astype(np.float64) * (1 << slots["level"][sel]),
                       slots["y"][sel].astype(np.float64) * (1 << slots["level"][sel])], axis=1)
     assert len(feats) > 150
+    lam = min_eig_per_level(oracle.pyr_build(tpl, 752, 3), feats)
+    posed = np.nan_to_num(lam, nan=-1.0).min(axis=1) >= 16.0
     got = gpu_track(ctx, tpl, img, 3, feats, mode=mode, eps=1e-3)
     want = cpu_track(tpl, img, 3, feats, mode=mode, eps=1e-3)
+    ok = compare(got, want, 1e-3, f"detected mode {mode}", where=posed)
+    assert ok.sum() > 0.7 * (want[1] == lk.TRACKED).sum()
     truth = lambda q: np.hypot(q[:, 0] - dx, q[:, 1] - dy) < 0.25  # noqa: E731
     good_cpu = (want[1] == lk.TRACKED) & truth(want[0])
     good_gpu = (got[1] == lk.TRACKED) & truth(got[0])
-    compare(got, want, 1e-3, f"detected mode {mode}", t_tol=0.02, where=good_cpu)
     assert good_cpu.sum() > 0.6 * len(feats)
     assert (good_cpu != good_gpu).sum() <= max(2, len(feats) // 50)
 
@@ -143,8 +153,8 @@ def test_track_many_features_sampled(ctx):
     assert np.isin(sg, [0, 1, 2, 3]).all() and np.isfinite(qg).all()
     idx = np.arange(0, 10000, 37)
     want = cpu_track(tpl, img, 4, feats[idx], mode=3, eps=1e-3)
-    near = np.hypot(want[0][:, 0] + 4.5, want[0][:, 1] - 6.25) < 0.5
-    compare((qg[idx], sg[idx], ig[idx]), want, 1e-3, "many features", where=near)
+    ok = compare((qg[idx], sg[idx], ig[idx]), want, 1e-3, "many features")
+    assert ok.sum() > 0.8 * len(idx)
     assert (sg == 0).sum() > 8000
 
 
@@ -220,8 +230,7 @@ def test_track_pyramid_depths(ctx, levels):
         img = wave_frame(1280, 720, seed=70 + levels, d=d, gain=gain, offset=off, wavelengths=wl)
         got = gpu_track(ctx, tpl, img, levels, feats, mode=mode, eps=1e-3)
         want = cpu_track(tpl, img, levels, feats, mode=mode, eps=1e-3)
-        near = np.hypot(want[0][:, 0] - d[0], want[0][:, 1] - d[1]) < 0.5
-        ok = compare(got, want, 1e-3, f"depth {levels} mode {mode}", where=near)
+        ok = compare(got, want, 1e-3, f"depth {levels} mode {mode}")
         assert ok.sum() > len(feats) // 2
 
 
@@ -234,8 +243,7 @@ def test_track_4k_frame(ctx):
     feats = np.stack([rng.uniform(0, 4096, 400), rng.uniform(0, 2160, 400)], axis=1)
     got = gpu_track(ctx, tpl, img, 5, feats, mode=3, eps=1e-3)
     want = cpu_track(tpl, img, 5, feats, mode=3, eps=1e-3)
-    near = np.hypot(want[0][:, 0] - 6.5, want[0][:, 1] + 4.25) < 0.5
-    ok = compare(got, want, 1e-3, "4k", where=near)
+    ok = compare(got, want, 1e-3, "4k")
     assert ok.sum() > 250
 
 
@@ -254,9 +262,7 @@ def test_track_fixed_step_count_matches_tightly(ctx, mode):
     ok = want[1] == lk.TRACKED
     assert ok.sum() > len(feats) // 2
     assert (got[2][ok] == 18).all() and (want[2][ok] == 18).all()
-    near = np.hypot(want[0][:, 0] - 1.75, want[0][:, 1] + 2.5) < 0.5
-    sel = ok & near
-    assert sel.sum() > len(feats) // 2
-    assert np.abs(got[0][sel, :2] - want[0][sel, :2]).max() < 2e-3
-    assert np.abs(got[0][sel, 2] - want[0][sel, 2]).max() < 1e-3
-    assert np.abs(got[0][sel, 3] - want[0][sel, 3]).max() < 0.1
+    # every tracked feature: only fp32 rounding separates the two sides
+    assert np.abs(got[0][ok, :2] - want[0][ok, :2]).max() < 2e-3
+    assert np.abs(got[0][ok, 2] - want[0][ok, 2]).max() < 1e-3
+    assert np.abs(got[0][ok, 3] - want[0][ok, 3]).max() < 0.1
