@@ -86,8 +86,8 @@ typedef struct {
     uint8_t reserved;
 } fast_feature;
 
-/* Corner score kinds (Section II-D names three; "the corner score is 0 if the
- * segment test fails" holds for each):
+/* Corner score kinds (Section II-D names three, and each is 0 where the
+ * segment test fails):
  *   FAST_SCORE_SADB  max(sum over brighter circle points of (p-c-t),
  *                        sum over darker circle points of (c-p-t)), the default;
  *   FAST_SCORE_SADA  the same two sums over only the circle points that lie on
@@ -117,7 +117,8 @@ typedef struct {
  * Errors: FAST_EINVAL (null out, bad device), FAST_EHIP, FAST_ENOMEM. */
 int fast_ctx_create(int hip_device, fast_ctx **out);
 
-/* Destroy a context after synchronising its outstanding work.  NULL is a no-op. */
+/* Destroy a context after its outstanding work has completed (its submissions'
+ * events; with a launched live plan, the whole device).  NULL is a no-op. */
 void fast_ctx_destroy(fast_ctx *ctx);
 
 /* Static description of a status code. */
@@ -140,8 +141,10 @@ int fast_grid_dims(int width, int height, int cell, int *gw, int *gh);
  * Errors: FAST_EINVAL (see fast_plane; level sizes must be floor halvings). */
 int fast_pyr_build(fast_ctx *ctx, const fast_plane *pyr, int levels, void *stream);
 
-/* Plain path, one frame: build levels 1..levels-1 into pyr[1..] and write one
- * fast_feature per grid cell into `out` (device, gw*gh slots, row-major).
+/* Plain path, one frame: the detector of Sections II-B to II-D and Algorithm 1
+ * (pyramid, FAST segment test and score with Eq. (1), 3x3 NMS, the per-cell
+ * maximum over all levels).  Builds levels 1..levels-1 into pyr[1..] and writes
+ * one fast_feature per grid cell into `out` (device, gw*gh slots, row-major).
  * Everything is enqueued on `stream`; no host synchronisation.
  * Errors: FAST_EINVAL for null pointers, levels not in 1..8, t not in 0..255,
  * n not in 1..16, cell < 1 or cell > 256 or cell % 2^(levels-1) != 0, a plane
@@ -257,7 +260,10 @@ int fast_plan_create(fast_ctx *ctx, const fast_job *jobs, int njobs, int flags, 
  * no event is recorded (the caller synchronises on the stream itself). */
 int fast_plan_launch(fast_ctx *ctx, int plan_id, void *stream, uint64_t *ticket);
 
-/* Release a resident batch (after its launches complete). */
+/* Release a resident batch.  Never waits: the plan's device memory and graph
+ * are freed once the launches already enqueued have completed (at a later
+ * fast_plan_create, or in fast_ctx_destroy).  The stream of the plan's last
+ * launch must still exist when this is called. */
 int fast_plan_destroy(fast_ctx *ctx, int plan_id);
 
 /* Launch-shape tuning (the autotuner's knobs), per context.

@@ -50,6 +50,21 @@ struct Plan {
     int njobs = 0;
     int total = 0, total_upper = 0, max_levels = 0, mw1 = 0, mh1 = 0;
     bool all_single = true;
+    bool launched = false;
+    hipStream_t last_stream = nullptr;   // launches of a plan are ordered on one stream
+};
+
+// Device memory that enqueued work may still read when its owner is released
+// (a destroyed plan, a staging buffer outgrown by a submission).  It is freed
+// once `done` has completed, at the next setup call that finds it so, or when
+// the context is destroyed: hipFree waits for the whole device, so it is kept
+// off the launch, submit and destroy paths.
+struct Retired {
+    void *dev[3] = {nullptr, nullptr, nullptr};
+    void *host = nullptr;                // pinned staging buffer
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;           // null: nothing enqueued reads it
 };
 
 }  // namespace
@@ -63,6 +78,7 @@ struct fast_ctx {
     uint64_t event_ticket[TICKET_RING] = {};
     TableSlot slots[TABLE_SLOTS];
     std::vector<Plan> plans;
+    std::vector<Retired> retired;
     hipStream_t capture_stream = nullptr;
 };
 
@@ -184,6 +200,46 @@ int record_ticket(fast_ctx *c, hipStream_t s, uint64_t *ticket) {
     return FAST_OK;
 }
 
+// Queue device memory for release once the work enqueued on `s` so far has
+// completed (s may be null when no work reads it).
+int retire(fast_ctx *c, Retired r, bool enqueued, hipStream_t s) {
+    if (enqueued) {
+        hipError_t e = hipEventCreateWithFlags(&r.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(r.done, s);
+        if (e != hipSuccess) return hip_fail(c, e, "retire event");
+    }
+    c->retired.push_back(r);
+    return FAST_OK;
+}
+
+void release(Retired &r) {
+    if (r.exec) (void)hipGraphExecDestroy(r.exec);
+    if (r.graph) (void)hipGraphDestroy(r.graph);
+    for (void *p : r.dev)
+        if (p) (void)hipFree(p);
+    if (r.host) (void)hipHostFree(r.host);
+    if (r.done) (void)hipEventDestroy(r.done);
+    r = Retired();
+}
+
+// Free retired memory whose readers have finished (setup calls only: hipFree
+// synchronises the device).  wait: block until every reader has finished.
+void reap(fast_ctx *c, bool wait) {
+    std::vector<Retired> keep;
+    for (Retired &r : c->retired) {
+        bool finished = !r.done;
+        if (!finished && wait) {
+            (void)hipEventSynchronize(r.done);
+            finished = true;
+        } else if (!finished) {
+            finished = hipEventQuery(r.done) != hipErrorNotReady;
+        }
+        if (finished) release(r);
+        else keep.push_back(r);
+    }
+    c->retired.swap(keep);
+}
+
 // 1 done, 0 pending, <0 error.
 int ticket_state(fast_ctx *c, uint64_t tk) {
     if (tk == 0 || tk >= c->next_ticket) return fail(c, FAST_EINVAL, "unknown ticket");
@@ -265,6 +321,26 @@ FG_API const char *fast_strerror(int status) {
 
 FG_API const char *fast_last_error(const fast_ctx *c) { return c ? c->err.c_str() : "no context"; }
 
+// Staging buffers of a submission slot, `cap` bytes each, and its queue
+// counters (zeroed).
+int slot_alloc(fast_ctx *c, TableSlot &S, size_t cap) {
+    hipError_t e = hipHostMalloc((void **)&S.host, cap, hipHostMallocDefault);
+    if (e != hipSuccess) { S.host = nullptr; return hip_fail(c, e, "hipHostMalloc job table"); }
+    e = hipMalloc((void **)&S.dev, cap);
+    if (e != hipSuccess) { S.dev = nullptr; return hip_fail(c, e, "hipMalloc job table"); }
+    S.cap = cap;
+    if (!S.counter) {
+        e = hipMalloc((void **)&S.counter, FG_COUNTER_WORDS * sizeof(unsigned));
+        if (e != hipSuccess) { S.counter = nullptr; return hip_fail(c, e, "hipMalloc counter"); }
+        e = hipMemset(S.counter, 0, FG_COUNTER_WORDS * sizeof(unsigned));
+        if (e != hipSuccess) return hip_fail(c, e, "hipMemset counter");
+    }
+    return FAST_OK;
+}
+
+// Default staging capacity of a slot: FAST_MAX_JOBS jobs and 65536 work items.
+size_t slot_default_cap() { return items_offset(FAST_MAX_JOBS) + sizeof(fg_item) * 65536; }
+
 FG_API int fast_ctx_create(int hip_device, fast_ctx **out) {
     if (!out) return FAST_EINVAL;
     *out = nullptr;
@@ -289,6 +365,15 @@ FG_API int fast_ctx_create(int hip_device, fast_ctx **out) {
             return FAST_EHIP;
         }
     }
+    // every submission slot is ready before the first submit, so fast_submit
+    // allocates nothing (unless a submission outgrows a slot)
+    for (auto &S : c->slots) {
+        if (slot_alloc(c, S, slot_default_cap()) != FAST_OK) {
+            const int rc = FAST_ENOMEM;
+            fast_ctx_destroy(c);
+            return rc;
+        }
+    }
     *out = c;
     return FAST_OK;
 }
@@ -296,7 +381,18 @@ FG_API int fast_ctx_create(int hip_device, fast_ctx **out) {
 FG_API void fast_ctx_destroy(fast_ctx *c) {
     if (!c) return;
     DeviceGuard g(c->device);
-    (void)hipDeviceSynchronize();
+    // wait for this context's own work: its outstanding submissions, the
+    // launches of its live plans and the readers of retired memory (the frees
+    // below then find the device idle as far as this context is concerned)
+    for (int i = 0; i < TICKET_RING; ++i)
+        if (c->events[i] && c->event_ticket[i]) (void)hipEventSynchronize(c->events[i]);
+    // a live plan records no event per launch; its stream may be gone by now,
+    // so its launches are waited for with the device (the frees below would
+    // wait for the device anyway)
+    bool plan_pending = false;
+    for (auto &p : c->plans) plan_pending = plan_pending || (p.live && p.launched);
+    if (plan_pending) (void)hipDeviceSynchronize();
+    reap(c, true);
     for (auto &p : c->plans) {
         if (p.exec) (void)hipGraphExecDestroy(p.exec);
         if (p.graph) (void)hipGraphDestroy(p.graph);
@@ -514,18 +610,6 @@ FG_API int fast_submit(fast_ctx *c, const fast_job *jobs, int njobs, void *strea
     if (slot < 0) return fail(c, FAST_EBUSY, "all job tables are in flight");
     DeviceGuard g(c->device);
     TableSlot &S = c->slots[slot];
-    if (!S.host) {
-        const size_t cap = items_offset(FAST_MAX_JOBS) + sizeof(fg_item) * 65536;
-        hipError_t e = hipHostMalloc((void **)&S.host, cap, hipHostMallocDefault);
-        if (e != hipSuccess) { S.host = nullptr; return hip_fail(c, e, "hipHostMalloc job table"); }
-        e = hipMalloc((void **)&S.dev, cap);
-        if (e != hipSuccess) { S.dev = nullptr; return hip_fail(c, e, "hipMalloc job table"); }
-        S.cap = cap;
-        e = hipMalloc((void **)&S.counter, FG_COUNTER_WORDS * sizeof(unsigned));
-        if (e != hipSuccess) { S.counter = nullptr; return hip_fail(c, e, "hipMalloc counter"); }
-        e = hipMemset(S.counter, 0, FG_COUNTER_WORDS * sizeof(unsigned));
-        if (e != hipSuccess) return hip_fail(c, e, "hipMemset counter");
-    }
     int total, total_upper, max_levels, mw1, mh1;
     bool all_single;
     // the staging buffer always has room for FAST_MAX_JOBS jobs
@@ -534,22 +618,24 @@ FG_API int fast_submit(fast_ctx *c, const fast_job *jobs, int njobs, void *strea
     const int nitems = total + total_upper;
     const size_t off = items_offset(njobs), bytes = off + sizeof(fg_item) * (size_t)nitems;
     if (bytes > S.cap) {
-        // the slot is idle, so its old buffers are no longer read by the device
-        const size_t cap = std::max(bytes, items_offset(FAST_MAX_JOBS) + sizeof(fg_item) * 65536);
-        uint8_t *host = nullptr, *dev = nullptr;
-        hipError_t e = hipHostMalloc((void **)&host, cap, hipHostMallocDefault);
-        if (e != hipSuccess) return hip_fail(c, e, "hipHostMalloc job table");
-        e = hipMalloc((void **)&dev, cap);
-        if (e != hipSuccess) {
-            (void)hipHostFree(host);
-            return hip_fail(c, e, "hipMalloc job table");
+        // the slot is idle (its last submission has finished), so nothing
+        // reads its old buffers; they are released at the next setup call
+        // rather than here, since hipFree would wait for the whole device
+        TableSlot grown;
+        grown.counter = S.counter;
+        int arc = slot_alloc(c, grown, std::max(bytes, slot_default_cap()));
+        if (arc != FAST_OK) {
+            if (grown.host) (void)hipHostFree(grown.host);
+            return arc;
         }
-        memcpy(host, S.host, off);
-        (void)hipHostFree(S.host);
-        (void)hipFree(S.dev);
-        S.host = host;
-        S.dev = dev;
-        S.cap = cap;
+        memcpy(grown.host, S.host, off);
+        Retired r;
+        r.dev[0] = S.dev;
+        r.host = S.host;
+        arc = retire(c, r, false, nullptr);
+        if (arc != FAST_OK) return arc;
+        grown.ticket = S.ticket;
+        S = grown;
     }
     const fg_job *jobs_dev = (const fg_job *)S.dev;
     const fg_item *items_dev = (const fg_item *)(S.dev + off);
@@ -603,6 +689,7 @@ FG_API int fast_plan_create(fast_ctx *c, const fast_job *jobs, int njobs, int fl
     int rc = build_table(c, jobs, njobs, table.data(), total, total_upper, max_levels, mw1, mh1, all_single);
     if (rc) return rc;
     DeviceGuard g(c->device);
+    reap(c, false);   // a setup call: release what destroyed plans left behind
     Plan p;
     p.njobs = njobs;
     p.total = total;
@@ -658,7 +745,9 @@ FG_API int fast_plan_launch(fast_ctx *c, int plan_id, void *stream, uint64_t *ti
         return fail(c, FAST_EINVAL, "unknown plan");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
-    const Plan &p = c->plans[plan_id];
+    Plan &p = c->plans[plan_id];
+    p.launched = true;
+    p.last_stream = s;
     hipError_t e = p.exec ? hipGraphLaunch(p.exec, s)
                           : fg_launch_batch(p.dev, p.items, p.njobs, p.total, p.total_upper, p.max_levels, p.mw1, p.mh1,
                                             p.all_single,
@@ -674,12 +763,15 @@ FG_API int fast_plan_destroy(fast_ctx *c, int plan_id) {
         return fail(c, FAST_EINVAL, "unknown plan");
     DeviceGuard g(c->device);
     Plan &p = c->plans[plan_id];
-    (void)hipDeviceSynchronize();
-    if (p.exec) (void)hipGraphExecDestroy(p.exec);
-    if (p.graph) (void)hipGraphDestroy(p.graph);
-    (void)hipFree(p.dev);
-    (void)hipFree(p.items);
-    (void)hipFree(p.counter);
+    // no host wait: the plan's memory and graph are released once the
+    // launches already enqueued (all on p.last_stream) have completed
+    Retired r;
+    r.dev[0] = p.dev;
+    r.dev[1] = p.items;
+    r.dev[2] = p.counter;
+    r.graph = p.graph;
+    r.exec = p.exec;
+    const int rc = retire(c, r, p.launched, p.last_stream);
     p = Plan();
-    return FAST_OK;
+    return rc;
 }

@@ -267,3 +267,49 @@ def test_batch_launch_shapes_with_deep_levels(ctx, shape):
         check_all(specs, pyrs, grids, want, f"shape {shape}")
     finally:
         ctx.reset_launch()
+
+
+def _hold_stream(stream, ms: float) -> None:
+    """Enqueue a bounded spin of about `ms` on `stream` (torch's sleep kernel,
+    which exits on its own), so that work enqueued behind it stays pending
+    for that long without any kernel of this library waiting on anything."""
+    probe = torch.cuda.Stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(probe):
+        e0.record()
+        torch.cuda._sleep(1_000_000)
+        e1.record()
+    e1.synchronize()
+    per_ms = 1_000_000 / max(e0.elapsed_time(e1), 1e-3)
+    with torch.cuda.stream(stream):
+        torch.cuda._sleep(int(per_ms * ms))
+
+
+def test_ninth_outstanding_submission_is_busy_and_wait_times_out(ctx, batch):
+    """Host-forced failure paths: with the stream held by a bounded spin, eight
+    submissions take every in-flight job table, so the ninth returns
+    FAST_EBUSY and enqueues nothing; fast_wait with a zero timeout returns
+    FAST_ETIMEDOUT; after the spin ends every submission completes, bit-exact,
+    and a new submission is accepted again."""
+    specs, frames, want = batch
+    stream = torch.cuda.Stream()
+    sets = [make_resident(specs[i:i + 1], frames[i:i + 1]) for i in range(9)]
+    torch.cuda.synchronize()
+    _hold_stream(stream, 400.0)
+    tickets = [ctx.submit(jobs, stream) for _, _, jobs in sets[:8]]
+    with pytest.raises(fastgrid.FastError) as ei:
+        ctx.submit(sets[8][2], stream)
+    assert ei.value.code == fastgrid.FAST_EBUSY
+    assert not ctx.poll(tickets[0])
+    rc = fastgrid.load().fast_wait(ctx.handle, tickets[0], 0)
+    assert rc == fastgrid.FAST_ETIMEDOUT
+    assert ctx.wait(tickets[0], 0) is False
+    assert ctx.wait(tickets[7], 30000)
+    assert all(ctx.poll(t) for t in tickets)
+    for i, (pyrs, grids, _) in enumerate(sets[:8]):
+        check_all(specs[i:i + 1], pyrs, grids, want[i:i + 1], f"held submission {i}")
+    # the rejected ninth enqueued nothing: its outputs are still zero
+    assert not sets[8][1][0].tensor.any()
+    tk = ctx.submit(sets[8][2], stream)
+    assert ctx.wait(tk, 30000)
+    check_all(specs[8:9], sets[8][0], sets[8][1], want[8:9], "ninth after the others")
