@@ -22,7 +22,10 @@ HIP_SOURCES = ["fastgrid_kernels.hip", "fasttrack_kernels.hip", "fastgrid_runtim
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Wall", "-Wno-unused-function",
-    # no packed-FP32 instructions anywhere in this library
+    # no packed-FP32 instructions (v_pk_add/mul/fma_f32) in the device code.
+    # The device pass honours this feature (tests/test_build_flags.py shows a
+    # float2 FMA becoming v_pk_fma_f32 without it and two FMAs with it); the
+    # host pass does not know it and warns that it ignores it
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fvisibility=hidden",
 ]

@@ -64,18 +64,28 @@ def trace(stats_csv: str) -> list[dict]:
                  "total_ns": int(float(r["TotalDurationNs"]))} for r in csv.DictReader(f)]
 
 
-def kernel_source_hash(name: str = "fastgrid_kernels.hip") -> str:
-    """sha256[:16] of a kernel source with comments and blank space removed,
-    so that a record stays valid across comment-only edits."""
+# What decides the detector's kernels and their launch: the kernels, the
+# shared declarations (sub-tile and fused-level constants) and the runtime
+# (launch defaults, region layout, work-item order).
+DETECT_SOURCES = ("fastgrid_kernels.hip", "fg_internal.h", "fastgrid_runtime.hip")
+
+
+def kernel_source_hash(names=DETECT_SOURCES) -> str:
+    """sha256[:16] of kernel and runtime sources with comments and blank space
+    removed, so that a record stays valid across comment-only edits."""
     import hashlib
     import re
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", name)
-    with open(path) as f:
-        text = f.read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    text = re.sub(r"//[^\n]*", "", text)
-    text = "\n".join(line.strip() for line in text.splitlines() if line.strip())
-    return hashlib.sha256(text.encode()).hexdigest()[:16]
+    if isinstance(names, str):
+        names = (names,)
+    parts = []
+    for name in names:
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", name)
+        with open(path) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        parts.append("\n".join(line.strip() for line in text.splitlines() if line.strip()))
+    return hashlib.sha256("\n".join(parts).encode()).hexdigest()[:16]
 
 
 def short_name(name: str) -> str:
@@ -98,7 +108,7 @@ def trace_md(stats_csv: str, command: str) -> str:
         f"Summary: `python -m paper_2003_13493_amd.profile_tools trace {stats_csv}`.",
         "detect_batch_kernel is one persistent launch over the whole 64-frame batch (pyramid levels 1-2",
         "are built inside it); detect_plain_kernel is the plain path, one launch per frame.",
-        f"Kernel source hash (sha256[:16] of the source without comments) = {kernel_source_hash()}.", "", *lines, ""])
+        f"Kernel source hash (sha256[:16] of the kernel and runtime sources without comments) = {kernel_source_hash()}.", "", *lines, ""])
 
 
 def counters(pmc_dir: str, name_part: str = "detect_batch_kernel") -> dict:
@@ -124,7 +134,7 @@ def track_md(trace_csv: str, command: str) -> str:
              f"Summary: `python -m paper_2003_13493_amd.profile_tools track {trace_csv}`.",
              "track_kernel is one launch per call, one wave64 per feature; the frames are two 752x480 crops of one",
              "synthetic scene moved by (3, -2), 3 levels, max 30 iterations per level, eps 0.01.",
-             f"Kernel source hash (sha256[:16] of the source without comments) = {track_source_hash()}.", "",
+             f"Kernel source hash (sha256[:16] of the kernel and runtime sources without comments) = {track_source_hash()}.", "",
              "| parameters | features | calls | average ns | min ns | max ns |", "|---|---|---|---|---|---|"]
     i = 0
     for mode in TRACK_MODES:
@@ -157,7 +167,7 @@ def track_counters_md(pmc_dir: str, command: str) -> str:
              f"Summary: `python -m paper_2003_13493_amd.profile_tools track-counters {pmc_dir}`.",
              "Medians over each configuration's timed dispatches, per wave (one wave is one feature).",
              "wait = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES; VALU active = SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES.",
-             f"Kernel source hash (sha256[:16] of the source without comments) = {track_source_hash()}.", "",
+             f"Kernel source hash (sha256[:16] of the kernel and runtime sources without comments) = {track_source_hash()}.", "",
              "| parameters | features | VALU instr / wave | SALU instr / wave | VMEM instr / wave | "
              "wave cycles / wave | wait | VALU active |", "|---|---|---|---|---|---|---|---|"]
     i = 0
@@ -220,6 +230,6 @@ if __name__ == "__main__":
             with open(sys.argv[3], "w") as f:
                 f.write("\n".join(["# SQ counters: batched detect kernel on the 64-frame batch", "",
                                     "Command (repo root):", "", "    " + sys.argv[4], "",
-                                    f"Kernel source hash (sha256[:16] of the source without comments) = {kernel_source_hash()}.", "",
+                                    f"Kernel source hash (sha256[:16] of the kernel and runtime sources without comments) = {kernel_source_hash()}.", "",
                                     *lines, ""]))
         print(json.dumps(rec, indent=1))
