@@ -233,6 +233,32 @@ int fast_track(fast_ctx *ctx, const fast_plane *tpl, const fast_plane *img, int 
 int fast_submit(fast_ctx *ctx, const fast_job *jobs, int njobs, void *stream,
                 uint64_t *ticket);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): fast_submit
+ * without any allocation.  The queue counters, job table and work items go
+ * to a fixed scratch array in device memory that the library holds on each
+ * device from the first fast_ctx_create there until the process ends
+ * (FAST_STATIC_SCRATCH_BYTES, about 334 KiB), through a pinned staging buffer
+ * the context set up at creation; the call then enqueues the same kernels as
+ * fast_submit.  The caller still owns every plane and output.
+ * Limits: njobs <= FAST_STATIC_MAX_JOBS and at most FAST_STATIC_MAX_ITEMS
+ * work items (regions of the default 64-pixel side, counted once more for
+ * jobs of more than 3 levels); beyond either, FAST_EINVAL and nothing is
+ * enqueued.
+ * The scratch is shared by every context and stream on the device and keeps
+ * the last call's contents (the counters are rewritten as zeros by each
+ * call): calls whose work overlaps on one device race.  Calls on one stream
+ * are ordered.  A call waits for the previous call's table copy to leave the
+ * staging buffer before it rewrites it.
+ * ticket may be NULL (no completion event); otherwise it works as for
+ * fast_submit.  Errors: as fast_submit, except FAST_EBUSY and FAST_ENOMEM,
+ * which it never returns. */
+#define FAST_STATIC_MAX_JOBS 256
+#define FAST_STATIC_MAX_ITEMS 32768
+#define FAST_STATIC_SCRATCH_BYTES 342272
+int fast_submit_static(fast_ctx *ctx, const fast_job *jobs, int njobs, void *stream,
+                       uint64_t *ticket);
+
 /* 1 if the submission has finished, 0 if still pending; never blocks.
  * Errors: FAST_EINVAL for an unknown ticket, FAST_EHIP for a device error. */
 int fast_poll(fast_ctx *ctx, uint64_t ticket);

@@ -69,6 +69,43 @@ struct Retired {
 
 }  // namespace
 
+// Device scratch of fast_submit_static: the queue counters, the job table
+// and the work items of one submission, in a file-scope array instead of
+// memory allocated per context.  Each device holds its own copy; host code
+// reaches it only through the address hipGetSymbolAddress returns for that
+// device (the array's name is a host-side stand-in, not a device address).
+namespace {
+constexpr size_t STATIC_COUNTER_BYTES = 256;   // FG_COUNTER_WORDS words, padded
+constexpr size_t static_items_offset(int njobs) { return STATIC_COUNTER_BYTES + ((sizeof(fg_job) * (size_t)njobs + 15) & ~(size_t)15); }
+constexpr size_t STATIC_BYTES = static_items_offset(FAST_STATIC_MAX_JOBS) + sizeof(fg_item) * FAST_STATIC_MAX_ITEMS;
+static_assert(FG_COUNTER_WORDS * sizeof(unsigned) <= STATIC_COUNTER_BYTES, "counter words fit their slot");
+static_assert(STATIC_COUNTER_BYTES % 256 == 0, "job table 256-byte aligned");
+static_assert(STATIC_BYTES == FAST_STATIC_SCRATCH_BYTES, "the header states the scratch size");
+constexpr int MAX_DEVICES = 64;
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[STATIC_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_addr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current (the caller's DeviceGuard makes it so).
+hipError_t scratch_address(int device, uint8_t **out) {
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_addr[device] = (uint8_t *)p;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
+}  // namespace
+
 struct fast_ctx {
     int device = 0;
     fg_launch launch{};
@@ -80,6 +117,13 @@ struct fast_ctx {
     std::vector<Plan> plans;
     std::vector<Retired> retired;
     hipStream_t capture_stream = nullptr;
+    // fast_submit_static: the device scratch address, a pinned staging buffer
+    // of STATIC_BYTES set up at creation, and the event that marks the last
+    // table copy out of it
+    uint8_t *static_dev = nullptr;
+    uint8_t *static_host = nullptr;
+    hipEvent_t static_copied = nullptr;
+    bool static_pending = false;
 };
 
 namespace {
@@ -374,6 +418,17 @@ FG_API int fast_ctx_create(int hip_device, fast_ctx **out) {
             return rc;
         }
     }
+    // the scratch array of fast_submit_static: its device address, looked up
+    // once per device, and the pinned buffer its tables are staged in
+    uint8_t *dev_scratch = nullptr;
+    hipError_t se = scratch_address(hip_device, &dev_scratch);
+    if (se == hipSuccess) se = hipHostMalloc((void **)&c->static_host, STATIC_BYTES, hipHostMallocDefault);
+    if (se == hipSuccess) se = hipEventCreateWithFlags(&c->static_copied, hipEventDisableTiming);
+    if (se != hipSuccess) {
+        fast_ctx_destroy(c);
+        return FAST_EHIP;
+    }
+    c->static_dev = dev_scratch;
     *out = c;
     return FAST_OK;
 }
@@ -405,6 +460,11 @@ FG_API void fast_ctx_destroy(fast_ctx *c) {
         if (s.dev) (void)hipFree(s.dev);
         if (s.counter) (void)hipFree(s.counter);
     }
+    if (c->static_copied) {
+        if (c->static_pending) (void)hipEventSynchronize(c->static_copied);
+        (void)hipEventDestroy(c->static_copied);
+    }
+    if (c->static_host) (void)hipHostFree(c->static_host);
     for (auto &e : c->events)
         if (e) (void)hipEventDestroy(e);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -650,6 +710,50 @@ FG_API int fast_submit(fast_ctx *c, const fast_job *jobs, int njobs, void *strea
     if (rc) return rc;
     S.ticket = *ticket;
     return FAST_OK;
+}
+
+FG_API int fast_submit_static(fast_ctx *c, const fast_job *jobs, int njobs, void *stream, uint64_t *ticket) {
+    if (!c) return FAST_EINVAL;
+    if (!jobs) return fail(c, FAST_EINVAL, "jobs is NULL");
+    if (njobs < 1 || njobs > FAST_STATIC_MAX_JOBS)
+        return fail(c, FAST_EINVAL, "njobs not in 1.." + std::to_string(FAST_STATIC_MAX_JOBS) +
+                                        " (the static scratch limit)");
+    if (!c->static_dev || !c->static_host) return fail(c, FAST_EINVAL, "context has no static scratch");
+    DeviceGuard g(c->device);
+    // the staging buffer is reused: the previous call's copy out of it must
+    // have run before it is rewritten
+    if (c->static_pending) {
+        const hipError_t e = hipEventSynchronize(c->static_copied);
+        if (e != hipSuccess) return hip_fail(c, e, "hipEventSynchronize (static staging)");
+        c->static_pending = false;
+    }
+    uint8_t *host = c->static_host;
+    int total, total_upper, max_levels, mw1, mh1;
+    bool all_single;
+    int rc = build_table(c, jobs, njobs, (fg_job *)(host + STATIC_COUNTER_BYTES), total, total_upper, max_levels,
+                         mw1, mh1, all_single);
+    if (rc) return rc;
+    const int nitems = total + total_upper;
+    if (nitems > FAST_STATIC_MAX_ITEMS)
+        return fail(c, FAST_EINVAL, "the jobs need " + std::to_string(nitems) + " work items, more than the " +
+                                        std::to_string(FAST_STATIC_MAX_ITEMS) + " the static scratch holds");
+    const size_t off = static_items_offset(njobs), bytes = off + sizeof(fg_item) * (size_t)nitems;
+    // the queue counters travel with the table, so they start at zero whatever
+    // an earlier call left in the scratch
+    memset(host, 0, STATIC_COUNTER_BYTES);
+    fill_items((const fg_job *)(host + STATIC_COUNTER_BYTES), njobs, (fg_item *)(host + off));
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *dev = c->static_dev;
+    hipError_t e = hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(c, e, "static table upload");
+    e = hipEventRecord(c->static_copied, s);
+    if (e != hipSuccess) return hip_fail(c, e, "hipEventRecord (static staging)");
+    c->static_pending = true;
+    e = fg_launch_batch((const fg_job *)(dev + STATIC_COUNTER_BYTES), (const fg_item *)(dev + off), njobs, total,
+                        total_upper, max_levels, mw1, mh1, all_single, (unsigned *)dev, c->launch, s);
+    if (e != hipSuccess) return hip_fail(c, e, "batch launch (static)");
+    if (!ticket) return FAST_OK;
+    return record_ticket(c, s, ticket);
 }
 
 FG_API int fast_poll(fast_ctx *c, uint64_t ticket) {

@@ -32,7 +32,7 @@ FAST_SCORE_SADB, FAST_SCORE_SADA, FAST_SCORE_MT = 0, 1, 2
 EXPORTS = ("fast_ctx_create", "fast_ctx_destroy", "fast_strerror", "fast_last_error",
            "fast_pyr_dims", "fast_grid_dims", "fast_pyr_build", "fast_detect_grid",
            "fast_detect_grid_score", "fast_score_maps", "fast_nms_grid",
-           "fast_submit", "fast_poll", "fast_wait", "fast_plan_create", "fast_plan_launch",
+           "fast_submit", "fast_submit_static", "fast_poll", "fast_wait", "fast_plan_create", "fast_plan_launch",
            "fast_plan_destroy", "fast_set_launch", "fast_track")
 
 
@@ -80,6 +80,7 @@ def load() -> ctypes.CDLL:
             "fast_detect_grid": ([vp, P, i32, i32, i32, i32, vp, vp], i32),
             "fast_detect_grid_score": ([vp, P, i32, i32, i32, i32, i32, vp, vp], i32),
             "fast_submit": ([vp, ctypes.POINTER(fast_job), i32, vp, u64p], i32),
+            "fast_submit_static": ([vp, ctypes.POINTER(fast_job), i32, vp, u64p], i32),
             "fast_poll": ([vp, ctypes.c_uint64], i32),
             "fast_wait": ([vp, ctypes.c_uint64, i32], i32),
             "fast_plan_create": ([vp, ctypes.POINTER(fast_job), i32, i32, ctypes.POINTER(i32)], i32),
@@ -156,6 +157,17 @@ def fast_submit(ctx, jobs, njobs: int, stream=None) -> int:
     tk = ctypes.c_uint64()
     _check(ctx, load().fast_submit(ctx, jobs, njobs, _stream(stream), ctypes.byref(tk)),
            "fast_submit")
+    return tk.value
+
+
+def fast_submit_static(ctx, jobs, njobs: int, stream=None, ticket: bool = True) -> int:
+    """Returns the ticket, or 0 when ticket=False (no completion event recorded)."""
+    if not ticket:
+        _check(ctx, load().fast_submit_static(ctx, jobs, njobs, _stream(stream), None), "fast_submit_static")
+        return 0
+    tk = ctypes.c_uint64()
+    _check(ctx, load().fast_submit_static(ctx, jobs, njobs, _stream(stream), ctypes.byref(tk)),
+           "fast_submit_static")
     return tk.value
 
 
@@ -370,6 +382,10 @@ class Context:
 
     def submit(self, jobs: ctypes.Array, stream=None) -> int:
         return fast_submit(self.handle, jobs, len(jobs), stream)
+
+    def submit_static(self, jobs: ctypes.Array, stream=None, ticket: bool = True) -> int:
+        """fast_submit through the library's fixed device scratch (no allocation)."""
+        return fast_submit_static(self.handle, jobs, len(jobs), stream, ticket)
 
     def poll(self, ticket: int) -> bool:
         return fast_poll(self.handle, ticket)
