@@ -1,6 +1,8 @@
 """The continuous-batching server on the GPU: every frame's result is the same
-alone and in the mix (tolerance 0), batched and plain modes agree, and
-admission by HBM budget rejects streams that do not fit."""
+alone and in the mix (tolerance 0) and equals the oracle's, batched and plain
+modes agree, admission by HBM budget keeps out streams that do not fit, and a
+stream kept out at the start is admitted once a departing stream releases its
+bytes, with every result still the oracle's."""
 import numpy as np
 import pytest
 
@@ -56,17 +58,15 @@ def test_each_result_same_alone_and_in_mix(ctx, batched, upload):
         st = srv.streams[r.stream]
         key = (r.stream, r.frame % len(st.pool))
         if key not in ref:
-            img = st.pool[key[1]].cpu().numpy()
-            ref[key] = alone(ctx, st.spec, img)
+            ref[key] = alone(ctx, st.spec, st.host_pool[key[1]])
         got = srv.results[r.rid].view(fastgrid.FEATURE_DTYPE)
         assert np.array_equal(got, ref[key]), (r.rid, key)
     # and every served (stream, frame) answer is the oracle's
-    assert len(ref) == sum(len(st.pool) for st in srv.streams)
+    assert len(ref) == sum(len(st.pool) for st in srv.streams if st is not None)
     for (s, k), want_gpu in ref.items():
-        st = srv.streams[s]
-        img = st.pool[k].cpu().numpy()
-        want, _ = oracle.detect_grid(img, st.spec.width, st.spec.levels, st.spec.t, st.spec.n,
-                                     st.spec.cell)
+        spec = srv.specs[s]
+        want, _ = oracle.detect_grid(srv.streams[s].host_pool[k], spec.width, spec.levels, spec.t,
+                                     spec.n, spec.cell)
         assert np.array_equal(want_gpu, want)
     srv.close()
 
@@ -76,8 +76,100 @@ def test_admission_by_hbm_budget(ctx):
     need = [serve.resident_bytes(s, 2, 2) for s in specs]
     budget = need[0] + need[1] + need[2] // 2
     srv = serve.Server(ctx, specs, pool_frames=2, slots_per_stream=2, hbm_budget=budget)
-    assert len(srv.streams) == 2 and len(srv.rejected) == 2
+    assert len(srv.admitted) == 2 and len(srv.rejected) == 2
+    assert [i for i, st in enumerate(srv.streams) if st is not None] == [0, 1]
     assert srv.resident <= budget
     stats = srv.run(0.2, seed=3)
-    assert stats["streams_admitted"] == 2 and stats["frames"] == stats["offered_frames"]
+    assert stats["streams_admitted"] == 2
+    # frames of the streams kept out are refused, the rest all served
+    assert stats["frames"] + stats["refused_frames"] == stats["offered_frames"]
+    assert set(stats["refused_by_stream"]) == {2, 3}
+    srv.close()
+
+
+def test_waiting_stream_admitted_when_another_leaves(ctx):
+    """Streams 0 and 1 fit at the start, 2 and 3 wait.  Stream 0 leaves at
+    0.15 s; once its last request completes its bytes are released and stream
+    2 (which fits in them) is admitted mid-run; 3 never fits.  Every served
+    frame, before and after the change, is the oracle's answer."""
+    specs = small_streams()
+    need = [serve.resident_bytes(s, 2, 2) for s in specs]
+    budget = need[1] + need[2]
+    assert need[0] <= need[2] and need[0] + need[1] + need[2] > budget and need[1] + need[3] > budget
+    srv = serve.Server(ctx, specs, pool_frames=2, slots_per_stream=2, hbm_budget=budget,
+                       max_batch=16, inflight=3, keep_results=True)
+    assert [i for i, st in enumerate(srv.streams) if st is not None] == [0, 1]
+    assert srv.waiting == [2, 3]
+    print("case serve join/leave", flush=True)
+    trace = []
+    stats = srv.run(0.5, seed=21, leave={0: 0.15}, trace=trace)
+    log = srv.admission_log
+    rel = [t for t, i, what in log if i == 0 and what == "released"]
+    adm = [t for t, i, what in log if i == 2 and what == "admitted"]
+    assert len(rel) == 1 and len(adm) == 1 and 0.15 <= rel[0] <= adm[0] < 0.5, log
+    assert srv.streams[0] is None and srv.streams[2] is not None and srv.streams[3] is None
+    assert srv.waiting == [3] and srv.resident == need[1] + need[2] <= budget
+    served = {s: [r for r in stats["requests"] if r.stream == s] for s in range(4)}
+    assert served[0] and all(r.arrival < 0.15 for r in served[0])
+    assert served[2] and all(r.arrival >= adm[0] for r in served[2])
+    assert not served[3] and stats["refused_by_stream"].get(3, 0) > 0
+    assert stats["refused_by_stream"].get(2, 0) > 0          # sent while still waiting
+    assert len(trace) == stats["batches"] and all(b["device_ms"] >= 0 for b in trace)
+    want = {}
+    for r in stats["requests"]:
+        spec = specs[r.stream]
+        k = r.frame % 2
+        if (r.stream, k) not in want:
+            want[(r.stream, k)] = oracle.detect_grid(spec.frame(k), spec.width, spec.levels, spec.t,
+                                                     spec.n, spec.cell)[0]
+        got = srv.results[r.rid].view(fastgrid.FEATURE_DTYPE)
+        assert np.array_equal(got, want[(r.stream, k)]), (r.rid, r.stream, k)
+    srv.close()
+
+
+class TexturedStream:
+    """A stream spec whose pool frames are crops of a textured scene along a
+    random walk (well-posed tracks, as in the front-end tests)."""
+
+    def __init__(self, index, width, height, levels, t, n, cell, rate_fps, seed):
+        from test_gpu_frontend_multi import sequence
+        self.index, self.width, self.height, self.levels = index, width, height, levels
+        self.t, self.n, self.cell, self.rate_fps = t, n, cell, rate_fps
+        self._frames = sequence(width, height, 3, seed)
+
+    def frame(self, k):
+        return self._frames[k % 3]
+
+
+def test_frontend_serving_matches_oracle_loop(ctx):
+    """Frontend serving: every stream's frames go through the detect-and-track
+    loop in arrival order, batched across streams, with device-resident
+    feature lists.  Each served step equals the oracle step applied to the
+    feature list the stream held before it (the previous step's result):
+    identical counts and decisions, kept positions within the tracker
+    tolerance, and exactly the oracle's added features."""
+    from test_gpu_frontend_multi import check_step, oracle_step
+    specs = [TexturedStream(0, 320, 240, 3, 10, 9, 16, 150.0, 91),
+             TexturedStream(1, 640, 480, 4, 8, 10, 32, 200.0, 92),
+             TexturedStream(2, 376, 240, 3, 15, 12, 16, 250.0, 93)]
+    fp = serve.FrontendParams(target=60, redetect_frac=0.5, mode=3, max_iter=30, eps=1e-3)
+    srv = serve.Server(ctx, specs, pool_frames=3, max_batch=16, inflight=3, keep_results=True, frontend=fp)
+    print("case serve frontend", flush=True)
+    stats = srv.run(0.1, seed=5)
+    assert stats["mode"] == "frontend" and stats["frames"] == stats["offered_frames"] > 20
+    tracked = 0
+    for s, spec in enumerate(specs):
+        reqs = sorted((r for r in stats["requests"] if r.stream == s), key=lambda r: r.arrival)
+        assert [r.done for r in reqs] == sorted(r.done for r in reqs)          # served in order
+        prev, feats_in = None, np.zeros((0, 2))
+        for f, r in enumerate(reqs):
+            info, feats = srv.results[r.rid]
+            info = (int(info[0]), bool(info[1]), int(info[2]))
+            feats = feats.astype(np.float64)
+            want = oracle_step(prev, spec.frame(r.frame), feats_in, spec.width, spec.levels, spec.t, spec.n,
+                               spec.cell, fp.target, fp.redetect_frac, fp.mode, fp.eps, kept_device=feats[:info[0]])
+            check_step(f"stream {s} frame {f}", info, feats, want)
+            tracked += info[0]
+            prev, feats_in = want[4], feats
+    assert tracked > 0
     srv.close()

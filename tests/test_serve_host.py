@@ -14,6 +14,15 @@ def test_admission_respects_budget_in_order():
     assert admitted == [] and rejected == [0]
 
 
+def test_waiting_streams_admitted_in_queue_order_as_they_fit():
+    need = [100, 300, 50, 200]
+    # room 260: 100 fits, 300 does not (keeps its place), 50 fits; 200 no longer fits
+    assert serve.admit_waiting([0, 1, 2, 3], need, 260) == ([0, 2], [1, 3])
+    assert serve.admit_waiting([1, 3], need, 500) == ([1, 3], [])
+    assert serve.admit_waiting([1, 3], need, 199) == ([], [1, 3])
+    assert serve.admit_waiting([], need, 10) == ([], [])
+
+
 def test_poisson_schedule_rates_and_order():
     sched = serve.poisson_arrivals([100.0, 1000.0], duration_s=20.0, seed=1)
     times = [t for t, _, _ in sched]
