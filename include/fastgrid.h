@@ -222,6 +222,54 @@ int fast_track(fast_ctx *ctx, const fast_plane *tpl, const fast_plane *img, int 
                const float *feats, float *q, int32_t *status, int32_t *iters, int nfeat, int mode,
                int max_iter, float eps, void *stream);
 
+/* The detect-and-track loop of the paper's tracker evaluation (Section III-D)
+ * for many camera streams in one call, with every feature list resident in
+ * device memory, so a frame needs no host round trip.  One job is one
+ * stream's step from its previous frame to the current one:
+ *   1. track the stream's live features (fast_track, from a zero initial
+ *      estimate; the live count is read from device memory);
+ *   2. keep the tracked ones (status FAST_TRACK_OK), in order, moved by their
+ *      estimated translation, and drop the rest;
+ *   3. when fewer than redetect_below remain, mark the cells that hold a kept
+ *      feature (cell of a level-0 position p: floor(p / cell), row-major) and
+ *      append the strongest winners of the other cells of this frame's
+ *      detection (score descending, then cell index ascending) at their
+ *      level-0 positions (x << level, y << level), up to the capacity.  Which
+ *      features a re-detection adds is not stated in the paper; this is the
+ *      reading taken.
+ * The caller detects on the current frame first (fast_submit or
+ * fast_detect_grid_score, which also builds the current pyramid's levels),
+ * on the same stream.  The paper's evaluation detects with SAD-A.
+ * tracking parameters (mode, max_iter, eps) are as for fast_track and shared
+ * by all jobs.  Asynchronous on `stream`; the job table travels in one copy
+ * from a context staging slot, like fast_submit (FAST_EBUSY when all are in
+ * flight); *ticket (may be NULL) works as for fast_submit.
+ * Errors: FAST_EINVAL for NULL jobs, njobs not in 1..FAST_MAX_JOBS, bad
+ * tracking parameters, or a job with bad planes (as fast_track; prev and cur
+ * of equal sizes), a cell rule violation, more than FAST_MAX_GRID_CELLS
+ * cells, NULL or misaligned (4 bytes) device arrays, capacity not in
+ * 1..FAST_MAX_TRACKS or redetect_below not in 0..capacity; nothing is then
+ * enqueued. */
+#define FAST_MAX_TRACKS 1024
+#define FAST_MAX_GRID_CELLS 65536
+typedef struct {
+    const fast_plane *prev;      /* host array of `levels` planes: the previous frame's pyramid,
+                                    or NULL on the stream's first frame (nothing is tracked) */
+    const fast_plane *cur;       /* host array of `levels` planes: this frame's pyramid, levels built */
+    int32_t levels;
+    const fast_feature *slots;   /* device: this frame's cell winners, gw*gh for cur[0]'s size and cell */
+    int32_t cell;
+    int32_t capacity;            /* target track count, 1..FAST_MAX_TRACKS */
+    int32_t redetect_below;      /* re-detect when fewer live tracks remain, 0..capacity */
+    float *feats;                /* device, capacity x 2: live features, level-0 (x, y); in and out */
+    int32_t *count;              /* device, 1: live features in feats; in and out */
+    float *q;                    /* device, capacity x 4: scratch (tracking estimates) */
+    int32_t *status;             /* device, capacity: scratch (tracking statuses) */
+    int32_t *info;               /* device, 4: out (tracked, re-detected 0/1, live, 0) */
+} fast_frontend_job;
+int fast_frontend_step(fast_ctx *ctx, const fast_frontend_job *jobs, int njobs, int mode, int max_iter,
+                       float eps, void *stream, uint64_t *ticket);
+
 /* Batched path: all `njobs` requests (1..FAST_MAX_JOBS, any mix of sizes and
  * parameters) run in one persistent launch fed by a device-side work queue.
  * The job table and its work-item list are enqueued on `stream` as one copy
@@ -304,6 +352,32 @@ int fast_plan_destroy(fast_ctx *ctx, int plan_id);
  *         batched kernel (1..16).
  * Errors: FAST_EINVAL for values out of range. */
 int fast_set_launch(fast_ctx *ctx, int region, int block, int persistent_blocks_per_cu);
+
+/* Tuned region sides for one-frame calls (the autotuner's table, keyed by
+ * frame shape).  An entry applies to fast_detect_grid*, fast_score_maps and
+ * fast_nms_grid calls on a frame of exactly its width, height, levels and
+ * cell; region is then the side of the square region one workgroup owns, in
+ * level-0 pixels, rounded as for fast_set_launch.  Shapes without an entry
+ * keep the default rule, and a nonzero region set with fast_set_launch
+ * overrides the table.  Batched submissions are not affected (they use the
+ * fast_set_launch shape).  The table is copied; n = 0 clears it.
+ * Errors: FAST_EINVAL for n not in 0..FAST_MAX_SHAPES, NULL entries with
+ * n > 0, an entry with bad sizes, levels or cell (as fast_detect_grid), a
+ * region not in 16..256, or a shape listed twice (the table is then left as
+ * it was). */
+typedef struct {
+    int32_t width, height, levels, cell;
+    int32_t region;
+} fast_shape_region;
+#define FAST_MAX_SHAPES 1024
+int fast_set_shape_table(fast_ctx *ctx, const fast_shape_region *entries, int n);
+
+/* The region side, in level-0 pixels after rounding to whole cells, that a
+ * one-frame call on a frame of this shape uses with the context's current
+ * settings (an explicit fast_set_launch side, the shape table, or the
+ * default rule).  Errors: FAST_EINVAL for NULL region or arguments that
+ * fast_detect_grid would reject. */
+int fast_shape_region_of(fast_ctx *ctx, int width, int height, int levels, int cell, int *region);
 
 #ifdef __cplusplus
 }

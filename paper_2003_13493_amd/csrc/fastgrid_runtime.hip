@@ -17,6 +17,8 @@
 static_assert(sizeof(fast_plane) == 24, "fast_plane layout is part of the ABI");
 static_assert(sizeof(fast_feature) == 8, "fast_feature layout is part of the ABI");
 static_assert(sizeof(fast_job) == 40, "fast_job layout is part of the ABI");
+static_assert(sizeof(fast_shape_region) == 20, "fast_shape_region layout is part of the ABI");
+static_assert(sizeof(fast_frontend_job) == 88, "fast_frontend_job layout is part of the ABI");
 
 namespace {
 
@@ -38,7 +40,7 @@ struct TableSlot {
     uint64_t ticket = 0;           // last submission that used this slot
 };
 
-size_t items_offset(int njobs) { return (sizeof(fg_job) * (size_t)njobs + 15) & ~(size_t)15; }
+constexpr size_t items_offset(int njobs) { return (sizeof(fg_job) * (size_t)njobs + 15) & ~(size_t)15; }
 
 struct Plan {
     bool live = false;
@@ -117,6 +119,8 @@ struct fast_ctx {
     std::vector<Plan> plans;
     std::vector<Retired> retired;
     hipStream_t capture_stream = nullptr;
+    // tuned region sides of one-frame calls, per frame shape (fast_set_shape_table)
+    std::vector<fast_shape_region> shapes;
     // fast_submit_static: the device scratch address, a pinned staging buffer
     // of STATIC_BYTES set up at creation, and the event that marks the last
     // table copy out of it
@@ -134,7 +138,8 @@ int fail(fast_ctx *c, int code, const std::string &msg) {
 }
 
 // Region layout of a one-frame call.  With an explicit side (plain_region
-// != 0) that side; otherwise the batch side, unless the frame has fewer
+// != 0) that side; else the tuned side of the frame's shape, if the shape
+// table has one; otherwise the batch side, unless the frame has fewer
 // regions than half the CUs and at most 3 levels: then 32-pixel regions give
 // 4x the workgroups at a still moderate halo cost (MI355X, 256 threads:
 // 640x480 L=3 10.8 us against 17.7 us; 1280x720, 240 regions, 16.6 against
@@ -145,6 +150,14 @@ void plain_layout(const fast_ctx *c, fg_job &j) {
         L.region = L.plain_region;
         fg_job_layout(j, L);
         return;
+    }
+    // a tuned side for this frame shape
+    for (const fast_shape_region &e : c->shapes) {
+        if (e.width == j.w[0] && e.height == j.h[0] && e.levels == j.levels && e.cell == j.cell) {
+            L.region = e.region;
+            fg_job_layout(j, L);
+            return;
+        }
     }
     fg_job_layout(j, L);
     if (j.levels <= 3 && j.rx * j.ry * 2 < L.num_cu) {
@@ -508,6 +521,49 @@ FG_API int fast_set_launch(fast_ctx *c, int region, int block, int bpc) {
     return FAST_OK;
 }
 
+FG_API int fast_set_shape_table(fast_ctx *c, const fast_shape_region *entries, int n) {
+    if (!c) return FAST_EINVAL;
+    if (n < 0 || n > FAST_MAX_SHAPES) return fail(c, FAST_EINVAL, "n not in 0..FAST_MAX_SHAPES");
+    if (n > 0 && !entries) return fail(c, FAST_EINVAL, "entries is NULL");
+    std::vector<fast_shape_region> table;
+    for (int i = 0; i < n; ++i) {
+        const fast_shape_region &e = entries[i];
+        const std::string at = "entry " + std::to_string(i) + ": ";
+        if (e.width < 1 || e.height < 1 || e.width > 65535 || e.height > 65535)
+            return fail(c, FAST_EINVAL, at + "width or height not in 1..65535");
+        if (e.levels < 1 || e.levels > FAST_MAX_LEVELS) return fail(c, FAST_EINVAL, at + "levels not in 1..8");
+        if ((e.width >> (e.levels - 1)) < 1 || (e.height >> (e.levels - 1)) < 1)
+            return fail(c, FAST_EINVAL, at + "a level of size 0");
+        if (check_params(c, e.levels, 0, 1, e.cell) != FAST_OK) return fail(c, FAST_EINVAL, at + c->err);
+        if (e.region < 16 || e.region > 256) return fail(c, FAST_EINVAL, at + "region not in 16..256");
+        for (const fast_shape_region &f : table)
+            if (f.width == e.width && f.height == e.height && f.levels == e.levels && f.cell == e.cell)
+                return fail(c, FAST_EINVAL, at + "shape listed twice");
+        table.push_back(e);
+    }
+    c->shapes.swap(table);
+    return FAST_OK;
+}
+
+FG_API int fast_shape_region_of(fast_ctx *c, int width, int height, int levels, int cell, int *region) {
+    if (!c) return FAST_EINVAL;
+    if (!region) return fail(c, FAST_EINVAL, "region is NULL");
+    if (width < 1 || height < 1 || width > 65535 || height > 65535)
+        return fail(c, FAST_EINVAL, "width or height not in 1..65535");
+    if (levels < 1 || levels > FAST_MAX_LEVELS) return fail(c, FAST_EINVAL, "levels not in 1..8");
+    int rc = check_params(c, levels, 0, 1, cell);
+    if (rc) return rc;
+    fg_job j;
+    memset(&j, 0, sizeof(j));
+    j.w[0] = width;
+    j.h[0] = height;
+    j.levels = levels;
+    j.cell = cell;
+    plain_layout(c, j);
+    *region = j.rcells * cell;
+    return FAST_OK;
+}
+
 FG_API int fast_pyr_build(fast_ctx *c, const fast_plane *pyr, int levels, void *stream) {
     if (!c) return FAST_EINVAL;
     int rc = check_pyr(c, pyr, levels);
@@ -754,6 +810,121 @@ FG_API int fast_submit_static(fast_ctx *c, const fast_job *jobs, int njobs, void
     if (e != hipSuccess) return hip_fail(c, e, "batch launch (static)");
     if (!ticket) return FAST_OK;
     return record_ticket(c, s, ticket);
+}
+
+// Track arguments of one pyramid pair (tpl, img) for tracking kernels.
+void fill_track_planes(fg_track_args &A, const fast_plane *tpl, const fast_plane *img, int levels) {
+    for (int k = 0; k < levels; ++k) {
+        A.tpl[k] = tpl[k].data;
+        A.img[k] = img[k].data;
+        A.w[k] = tpl[k].width;
+        A.h[k] = tpl[k].height;
+        A.tpitch[k] = tpl[k].pitch;
+        A.ipitch[k] = img[k].pitch;
+    }
+    A.levels = levels;
+}
+
+bool aligned4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
+
+int check_track_params(fast_ctx *c, int mode, int max_iter, float eps) {
+    if (mode & ~(FAST_TRACK_GAIN | FAST_TRACK_OFFSET)) return fail(c, FAST_EINVAL, "unknown mode bits");
+    if (max_iter < 0 || max_iter > 1000) return fail(c, FAST_EINVAL, "max_iter not in 0..1000");
+    if (!(eps >= 0.0f) || eps > 1e30f) return fail(c, FAST_EINVAL, "eps not a finite value >= 0");
+    return FAST_OK;
+}
+
+// A free submission slot (its last submission has finished), or -1.
+int free_slot(fast_ctx *c, int &slot) {
+    slot = -1;
+    for (int i = 0; i < TABLE_SLOTS && slot < 0; ++i) {
+        const uint64_t tk = c->slots[i].ticket;
+        if (tk == 0) slot = i;
+        else {
+            const int st = ticket_state(c, tk);
+            if (st < 0) return st;
+            if (st == 1) slot = i;
+        }
+    }
+    return FAST_OK;
+}
+
+FG_API int fast_frontend_step(fast_ctx *c, const fast_frontend_job *jobs, int njobs, int mode, int max_iter,
+                              float eps, void *stream, uint64_t *ticket) {
+    if (!c) return FAST_EINVAL;
+    if (!jobs) return fail(c, FAST_EINVAL, "jobs is NULL");
+    if (njobs < 1 || njobs > FAST_MAX_JOBS) return fail(c, FAST_EINVAL, "njobs not in 1..4096");
+    int rc = check_track_params(c, mode, max_iter, eps);
+    if (rc) return rc;
+    int slot;
+    rc = free_slot(c, slot);
+    if (rc) return rc;
+    if (slot < 0) return fail(c, FAST_EBUSY, "all job tables are in flight");
+    TableSlot &S = c->slots[slot];
+    static_assert(sizeof(fg_fe_job) * FAST_MAX_JOBS <= items_offset(FAST_MAX_JOBS) + sizeof(fg_item) * 65536,
+                  "a slot's default staging holds FAST_MAX_JOBS front-end jobs");
+    fg_fe_job *table = (fg_fe_job *)S.host;
+    int total_slots = 0;
+    for (int i = 0; i < njobs; ++i) {
+        const fast_frontend_job &q = jobs[i];
+        const std::string at = "job " + std::to_string(i) + ": ";
+        rc = check_pyr(c, q.cur, q.levels);
+        if (rc) return fail(c, rc, at + c->err);
+        if (q.prev) {
+            rc = check_pyr(c, q.prev, q.levels);
+            if (rc) return fail(c, rc, at + c->err);
+            if (q.prev[0].width != q.cur[0].width || q.prev[0].height != q.cur[0].height)
+                return fail(c, FAST_EINVAL, at + "previous and current sizes differ");
+        }
+        rc = check_params(c, q.levels, 0, 1, q.cell);
+        if (rc) return fail(c, rc, at + c->err);
+        const long gw = (q.cur[0].width + q.cell - 1) / q.cell, gh = (q.cur[0].height + q.cell - 1) / q.cell;
+        if (gw * gh > FAST_MAX_GRID_CELLS) return fail(c, FAST_EINVAL, at + "more than FAST_MAX_GRID_CELLS cells");
+        if (!q.slots || !q.feats || !q.count || !q.q || !q.status || !q.info)
+            return fail(c, FAST_EINVAL, at + "a device array is NULL");
+        if (((uintptr_t)q.slots & 7u) || !aligned4(q.feats) || !aligned4(q.count) || !aligned4(q.q) ||
+            !aligned4(q.status) || !aligned4(q.info))
+            return fail(c, FAST_EINVAL, at + "a device array is misaligned");
+        if (q.capacity < 1 || q.capacity > FAST_MAX_TRACKS)
+            return fail(c, FAST_EINVAL, at + "capacity not in 1..FAST_MAX_TRACKS");
+        if (q.redetect_below < 0 || q.redetect_below > q.capacity)
+            return fail(c, FAST_EINVAL, at + "redetect_below not in 0..capacity");
+        fg_fe_job &J = table[i];
+        memset(&J, 0, sizeof(J));
+        fill_track_planes(J.A, q.prev ? q.prev : q.cur, q.cur, q.levels);
+        J.A.feats = q.feats;
+        J.A.q = q.q;
+        J.A.status = q.status;
+        J.A.iters = nullptr;
+        J.A.nfeat = 0;
+        J.A.mode = mode;
+        J.A.max_iter = max_iter;
+        J.A.eps = eps;
+        J.slots = q.slots;
+        J.count = q.count;
+        J.info = q.info;
+        J.cell = q.cell;
+        J.gw = (int32_t)gw;
+        J.gh = (int32_t)gh;
+        J.capacity = q.capacity;
+        J.redetect_below = q.redetect_below;
+        J.has_prev = q.prev ? 1 : 0;
+        J.feat_base = total_slots;
+        total_slots += q.capacity;
+    }
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = sizeof(fg_fe_job) * (size_t)njobs;
+    hipError_t e = hipMemcpyAsync(S.dev, S.host, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(c, e, "front-end table upload");
+    e = fg_launch_frontend((const fg_fe_job *)S.dev, njobs, total_slots, s);
+    if (e != hipSuccess) return hip_fail(c, e, "front-end launch");
+    uint64_t tk = 0;
+    rc = record_ticket(c, s, &tk);
+    if (rc) return rc;
+    S.ticket = tk;
+    if (ticket) *ticket = tk;
+    return FAST_OK;
 }
 
 FG_API int fast_poll(fast_ctx *c, uint64_t ticket) {

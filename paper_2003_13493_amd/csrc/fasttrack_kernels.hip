@@ -204,13 +204,17 @@ __device__ void track_level(const fg_track_args &A, int k, float pxf, int pxi, f
     }
 }
 
-__global__ void __launch_bounds__(64 * TRACK_WAVES) track_kernel(fg_track_args A) {
-    // the wave's feature, provably uniform: its loads become scalar loads and
-    // the tests and loops on its position become scalar branches
-    const int f = __builtin_amdgcn_readfirstlane(blockIdx.x * TRACK_WAVES + (int)(threadIdx.x >> 6));
-    if (f >= A.nfeat) return;   // whole waves leave together
+// Track feature f of A from its initial estimate (A.q, or zero when
+// zero_init) and write the estimate, status and iteration count.
+__device__ void track_feature(const fg_track_args &A, int f, bool zero_init) {
     const float fx = A.feats[2 * f], fy = A.feats[2 * f + 1];
-    float tx = A.q[4 * f], ty = A.q[4 * f + 1], alpha = A.q[4 * f + 2], beta = A.q[4 * f + 3];
+    float tx = 0.0f, ty = 0.0f, alpha = 0.0f, beta = 0.0f;
+    if (!zero_init) {
+        tx = A.q[4 * f];
+        ty = A.q[4 * f + 1];
+        alpha = A.q[4 * f + 2];
+        beta = A.q[4 * f + 3];
+    }
     int total = 0, status = FAST_TRACK_OK;
     for (int k = A.levels - 1; k >= 0; --k) {
         const float scale = ldexpf(1.0f, k);
@@ -242,7 +246,242 @@ __global__ void __launch_bounds__(64 * TRACK_WAVES) track_kernel(fg_track_args A
     }
 }
 
+__global__ void __launch_bounds__(64 * TRACK_WAVES) track_kernel(fg_track_args A) {
+    // the wave's feature, provably uniform: its loads become scalar loads and
+    // the tests and loops on its position become scalar branches
+    const int f = __builtin_amdgcn_readfirstlane(blockIdx.x * TRACK_WAVES + (int)(threadIdx.x >> 6));
+    if (f >= A.nfeat) return;   // whole waves leave together
+    track_feature(A, f, false);
+}
+
+// ---------------------------------------------------------------------------
+// The detect-and-track loop of many camera streams (Section III-D's tracker
+// evaluation, one step per stream), with every feature list resident in
+// device memory.
+//
+// track_batch_kernel: one wave per feature slot of every job; a slot past the
+// job's live count (read from device memory) leaves at once.  Every track
+// starts from a zero estimate.
+
+// Atomic load of a counter another launch wrote (not through the scalar cache).
+__device__ __forceinline__ int load_count(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(64) track_batch_kernel(const fg_fe_job *__restrict__ jobs, int njobs) {
+    const int b = (int)blockIdx.x;
+    // the job whose slot range holds b: the last one with feat_base <= b
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].feat_base <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const fg_fe_job &J = jobs[lo];
+    const int f = b - J.feat_base;
+    if (!J.has_prev || f >= J.capacity) return;
+    const int n = __builtin_amdgcn_readfirstlane(load_count(J.count));
+    if (f >= n) return;
+    track_feature(J.A, f, true);
+}
+
+// frontend_update_kernel: one workgroup per job, after its tracking.
+//   1. the tracked features (status OK) move by their estimate and are kept
+//      in order; the others are dropped;
+//   2. when fewer than redetect_below remain, the cells holding a kept
+//      feature are marked taken, and the strongest cell winners of the other
+//      cells (score descending, then cell index ascending) are appended up to
+//      the capacity, at their level-0 positions (x << level, y << level);
+//   3. the live count and (tracked, redetected, live) are written.
+constexpr int FE_THREADS = 256;
+constexpr int FE_MAX_SCORE = 4096;   // scores are at most 4080
+static_assert(FAST_MAX_TRACKS <= 1024 && FAST_MAX_GRID_CELLS <= 65536, "LDS sizes below");
+
+// Inclusive prefix sum over the workgroup of one int per thread; `tot`
+// receives the total.  Uses wave DPP scans and one LDS word per wave.
+__device__ int block_scan(int v, int *wsum, int &tot) {
+    int x = v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int before = 0;
+    tot = 0;
+#pragma unroll
+    for (int w = 0; w < FE_THREADS / 64; ++w) {
+        const int s = wsum[w];
+        before += w < wave ? s : 0;
+        tot += s;
+    }
+    return x + before;
+}
+
+__global__ void __launch_bounds__(FE_THREADS) frontend_update_kernel(const fg_fe_job *__restrict__ jobs) {
+    __shared__ float2 kept[FAST_MAX_TRACKS];
+    __shared__ uint32_t taken[FAST_MAX_GRID_CELLS / 32];
+    __shared__ int hist[FE_MAX_SCORE];
+    __shared__ uint32_t sel[FAST_MAX_TRACKS];
+    __shared__ int wsum[FE_THREADS / 64];
+    __shared__ int s_nsel, s_all, s_sstar, s_at;
+    const fg_fe_job &J = jobs[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int cap = J.capacity;
+    const int n = J.has_prev ? min(load_count(J.count), cap) : 0;
+    // 1. keep the tracked features, in order, at their new positions
+    int live = 0;
+    for (int base = 0; base < n; base += FE_THREADS) {
+        const int i = base + tid;
+        const bool keep = i < n && J.A.status[i] == FAST_TRACK_OK;
+        float2 p = make_float2(0.0f, 0.0f);
+        if (keep) p = make_float2(J.A.feats[2 * i] + J.A.q[4 * i], J.A.feats[2 * i + 1] + J.A.q[4 * i + 1]);
+        int tot;
+        const int incl = block_scan(keep ? 1 : 0, wsum, tot);
+        if (keep) kept[live + incl - 1] = p;
+        live += tot;
+    }
+    // every thread has read the count and the kept list is complete before
+    // anyone reads the list or thread 0 rewrites the count
+    __syncthreads();
+    const int tracked = live;
+    const bool redetect = live < J.redetect_below;
+    const int ncells = J.gw * J.gh;
+    int nsel = 0;
+    if (redetect && live < cap) {
+        // 2a. taken cells and the score histogram of the free winners
+        for (int i = tid; i < (ncells + 31) / 32; i += FE_THREADS) taken[i] = 0u;
+        for (int i = tid; i < FE_MAX_SCORE; i += FE_THREADS) hist[i] = 0;
+        if (tid == 0) {
+            s_all = 1;
+            s_sstar = 1;
+            s_at = 0;
+            s_nsel = 0;
+        }
+        __syncthreads();
+        for (int i = tid; i < live; i += FE_THREADS) {
+            const float2 p = kept[i];
+            const long cx = (long)floorf(p.x / (float)J.cell), cy = (long)floorf(p.y / (float)J.cell);
+            const long c = cy * J.gw + cx;
+            if (c >= 0 && c < ncells) atomicOr(&taken[c >> 5], 1u << (c & 31));
+        }
+        __syncthreads();
+        for (int i = tid; i < ncells; i += FE_THREADS) {
+            const int sc = J.slots[i].score;
+            if (sc > 0 && !((taken[i >> 5] >> (i & 31)) & 1u)) atomicAdd(&hist[sc], 1);
+        }
+        __syncthreads();
+        // 2b. the score s* at which the count of free winners from the top
+        // reaches k = capacity - live: every winner above s* is taken, and the
+        // first ones in cell order at s*.  Thread i sums the 16 bins from
+        // score 4095 - 16 i down; a scan over threads counts from the top.
+        const int k = cap - live;
+        constexpr int PER = FE_MAX_SCORE / FE_THREADS;
+        const int top = FE_MAX_SCORE - 1 - tid * PER;
+        int mine = 0;
+        for (int j = 0; j < PER; ++j) mine += hist[top - j];
+        int tot;
+        const int incl = block_scan(mine, wsum, tot);
+        const int excl = incl - mine;
+        if (tot > k && excl < k && incl >= k) {   // exactly one thread
+            int acc = excl;
+            for (int j = 0; j < PER; ++j) {
+                const int h = hist[top - j];
+                if (acc + h >= k) {
+                    s_sstar = top - j;
+                    s_at = k - acc;
+                    s_all = 0;
+                    break;
+                }
+                acc += h;
+            }
+        }
+        __syncthreads();
+        const bool take_all = s_all != 0;
+        const int sstar = s_sstar, at = s_at;
+        // 2c. gather the chosen winners' keys (score << 16 | 0xFFFF - cell):
+        // every free winner above s* (or every one), and the first `at` at
+        // s* in cell order
+        int eq_seen = 0;
+        for (int base = 0; base < ncells; base += FE_THREADS) {
+            const int i = base + tid;
+            int sc = 0;
+            if (i < ncells) {
+                sc = J.slots[i].score;
+                if ((taken[i >> 5] >> (i & 31)) & 1u) sc = 0;
+            }
+            const bool hi = sc > 0 && (take_all || sc > sstar);
+            const bool eq = !take_all && sc > 0 && sc == sstar;
+            int tot;
+            const int incl = block_scan(eq ? 1 : 0, wsum, tot);
+            const bool pick = hi || (eq && eq_seen + incl <= at);
+            eq_seen += tot;
+            if (pick) {
+                const int slot = atomicAdd(&s_nsel, 1);
+                sel[slot] = ((uint32_t)sc << 16) | (0xFFFFu - (uint32_t)i);
+            }
+        }
+        __syncthreads();
+        nsel = s_nsel;
+        // 2d. order them: bitonic sort, descending, over the next power of two
+        int m = 1;
+        while (m < nsel) m <<= 1;
+        for (int i = nsel + tid; i < m; i += FE_THREADS) sel[i] = 0u;
+        __syncthreads();
+        for (int size = 2; size <= m; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int i = tid; i < m; i += FE_THREADS) {
+                    const int j = i ^ stride;
+                    if (j > i) {
+                        const uint32_t a = sel[i], b = sel[j];
+                        const bool desc = (i & size) == 0;
+                        if (desc ? a < b : a > b) {
+                            sel[i] = b;
+                            sel[j] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+    // 3. write the list back: kept features, then the new ones (the list is
+    // the job's own output; the tracking arguments only read it)
+    float *const feats = const_cast<float *>(J.A.feats);
+    for (int i = tid; i < live; i += FE_THREADS) {
+        feats[2 * i] = kept[i].x;
+        feats[2 * i + 1] = kept[i].y;
+    }
+    for (int r = tid; r < nsel; r += FE_THREADS) {
+        const int cellidx = (int)(0xFFFFu - (sel[r] & 0xFFFFu));
+        const fast_feature w = J.slots[cellidx];
+        feats[2 * (live + r)] = (float)((int)w.x << w.level);
+        feats[2 * (live + r) + 1] = (float)((int)w.y << w.level);
+    }
+    if (tid == 0) {
+        *J.count = live + nsel;
+        J.info[0] = tracked;
+        J.info[1] = redetect ? 1 : 0;
+        J.info[2] = live + nsel;
+        J.info[3] = 0;
+    }
+}
+
 }  // namespace
+
+hipError_t fg_launch_frontend(const fg_fe_job *jobs_dev, int njobs, int total_slots, hipStream_t s) {
+    if (total_slots > 0) {
+        hipLaunchKernelGGL(track_batch_kernel, dim3(total_slots), dim3(64), 0, s, jobs_dev, njobs);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(frontend_update_kernel, dim3(njobs), dim3(FE_THREADS), 0, s, jobs_dev);
+    return hipGetLastError();
+}
 
 hipError_t fg_launch_track(const fg_track_args &A, hipStream_t s) {
     if (A.nfeat <= 0) return hipSuccess;

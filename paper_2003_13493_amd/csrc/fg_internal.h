@@ -55,6 +55,26 @@ struct fg_track_args {
 };
 hipError_t fg_launch_track(const fg_track_args &A, hipStream_t s);
 
+// One camera stream's step of the detect-and-track loop (fast_frontend_step):
+// tracking arguments (tpl = previous pyramid, img = current; feats, q and
+// status hold `capacity` entries; nfeat unused: the live count is *count),
+// this frame's cell winners, and the selection rule.
+struct fg_fe_job {
+    fg_track_args A;
+    const fast_feature *slots;   // gw*gh cell winners of the current frame
+    int32_t *count;              // live features: in, tracked from the previous frame; out, after the step
+    int32_t *info;               // out: tracked, re-detected (0/1), live, 0
+    int32_t cell, gw, gh;
+    int32_t capacity;            // the target track count
+    int32_t redetect_below;      // re-detect when fewer live tracks remain
+    int32_t has_prev;            // 0 on a stream's first frame: nothing to track
+    int32_t feat_base;           // first wave of this job in the tracking launch
+};
+
+// Tracking of every job's live features (one wave per feature slot, total_slots
+// = sum of capacities), then the update of every job's feature list.
+hipError_t fg_launch_frontend(const fg_fe_job *jobs_dev, int njobs, int total_slots, hipStream_t s);
+
 // Plain path: one frame.  Enqueues the pyramid (levels 1..L-1) and detection.
 hipError_t fg_launch_plain(const fg_job &j, const fg_launch &L, hipStream_t s);
 

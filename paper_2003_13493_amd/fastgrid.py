@@ -33,7 +33,8 @@ EXPORTS = ("fast_ctx_create", "fast_ctx_destroy", "fast_strerror", "fast_last_er
            "fast_pyr_dims", "fast_grid_dims", "fast_pyr_build", "fast_detect_grid",
            "fast_detect_grid_score", "fast_score_maps", "fast_nms_grid",
            "fast_submit", "fast_submit_static", "fast_poll", "fast_wait", "fast_plan_create", "fast_plan_launch",
-           "fast_plan_destroy", "fast_set_launch", "fast_track")
+           "fast_plan_destroy", "fast_set_launch", "fast_track", "fast_set_shape_table",
+           "fast_shape_region_of", "fast_frontend_step")
 
 
 class fast_plane(ctypes.Structure):
@@ -45,6 +46,24 @@ class fast_job(ctypes.Structure):
     _fields_ = [("pyr", ctypes.POINTER(fast_plane)), ("levels", ctypes.c_int32),
                 ("t", ctypes.c_int32), ("n", ctypes.c_int32), ("cell", ctypes.c_int32),
                 ("out", ctypes.c_void_p), ("score", ctypes.c_int32)]
+
+
+class fast_shape_region(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("cell", ctypes.c_int32), ("region", ctypes.c_int32)]
+
+
+FAST_MAX_SHAPES = 1024
+FAST_MAX_TRACKS = 1024
+FAST_MAX_GRID_CELLS = 65536
+
+
+class fast_frontend_job(ctypes.Structure):
+    _fields_ = [("prev", ctypes.POINTER(fast_plane)), ("cur", ctypes.POINTER(fast_plane)),
+                ("levels", ctypes.c_int32), ("slots", ctypes.c_void_p), ("cell", ctypes.c_int32),
+                ("capacity", ctypes.c_int32), ("redetect_below", ctypes.c_int32),
+                ("feats", ctypes.c_void_p), ("count", ctypes.c_void_p), ("q", ctypes.c_void_p),
+                ("status", ctypes.c_void_p), ("info", ctypes.c_void_p)]
 
 
 class FastError(RuntimeError):
@@ -91,6 +110,10 @@ def load() -> ctypes.CDLL:
             "fast_nms_grid": ([vp, ctypes.POINTER(vp), ctypes.POINTER(i32), i32, i32, i32, i32, i32, vp, vp],
                               i32),
             "fast_track": ([vp, P, P, i32, vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp], i32),
+            "fast_set_shape_table": ([vp, ctypes.POINTER(fast_shape_region), i32], i32),
+            "fast_shape_region_of": ([vp, i32, i32, i32, i32, ctypes.POINTER(i32)], i32),
+            "fast_frontend_step": ([vp, ctypes.POINTER(fast_frontend_job), i32, i32, i32, ctypes.c_float, vp,
+                                    u64p], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -211,6 +234,27 @@ def fast_set_launch(ctx, region: int, block: int, blocks_per_cu: int) -> None:
     _check(ctx, load().fast_set_launch(ctx, region, block, blocks_per_cu), "fast_set_launch")
 
 
+def fast_set_shape_table(ctx, entries) -> None:
+    """entries: iterable of (width, height, levels, cell, region)."""
+    entries = list(entries)
+    arr = (fast_shape_region * max(1, len(entries)))(*[fast_shape_region(*e) for e in entries])
+    _check(ctx, load().fast_set_shape_table(ctx, arr, len(entries)), "fast_set_shape_table")
+
+
+def fast_shape_region_of(ctx, width: int, height: int, levels: int, cell: int) -> int:
+    r = ctypes.c_int()
+    _check(ctx, load().fast_shape_region_of(ctx, width, height, levels, cell, ctypes.byref(r)),
+           "fast_shape_region_of")
+    return r.value
+
+
+def fast_frontend_step(ctx, jobs, njobs: int, mode: int, max_iter: int, eps: float, stream=None) -> int:
+    tk = ctypes.c_uint64()
+    _check(ctx, load().fast_frontend_step(ctx, jobs, njobs, mode, max_iter, eps, _stream(stream),
+                                          ctypes.byref(tk)), "fast_frontend_step")
+    return tk.value
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -310,8 +354,19 @@ class Grid:
 class Context:
     """Owns a fast_ctx; detect() is the plain path, submit()/plan_*() the batched one."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tuned: bool = True):
+        """tuned: load the launch-shape table shipped next to the library
+        (tune.TABLE_PATH) when it was tuned on this device kind."""
         self.handle = fast_ctx_create(device)
+        self.tuned = None
+        if tuned:
+            import torch
+            from . import tune
+            arch = torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
+            table = tune.load(device=arch)
+            if table is not None:
+                tune.apply(self, table)
+                self.tuned = tune.TABLE_PATH
 
     def close(self):
         if self.handle:
@@ -327,6 +382,14 @@ class Context:
     def set_launch(self, region: int, block: int, blocks_per_cu: int) -> None:
         """region 0 selects the default: 64, or 32 for one small frame."""
         fast_set_launch(self.handle, region, block, blocks_per_cu)
+
+    def set_shape_table(self, entries) -> None:
+        """Tuned region sides of one-frame calls: (width, height, levels, cell, region) rows."""
+        fast_set_shape_table(self.handle, entries)
+
+    def shape_region(self, width: int, height: int, levels: int, cell: int) -> int:
+        """The region side a one-frame call on this frame shape uses now."""
+        return fast_shape_region_of(self.handle, width, height, levels, cell)
 
     def reset_launch(self) -> None:
         """The launch shape of a new context."""

@@ -10,10 +10,15 @@ track the live features from the previous frame's pyramid, drop the lost
 ones, and if fewer than ``redetect_frac * target`` remain, detect on the new
 frame and add the strongest cell winners whose cells hold no live track
 (strongest first; equal scores by cell index) up to the target.  All image
-work runs in the HIP library; the host keeps the short feature list.
+work runs in the HIP library.  `Frontend` keeps one camera's short feature
+list on the host; `MultiFrontend` runs the same loop for many cameras with
+every feature list in device memory (fast_frontend_step), so a step needs no
+host round trip.
 """
 from __future__ import annotations
 
+import ctypes
+import math
 import time
 
 import numpy as np
@@ -100,3 +105,88 @@ class Frontend:
         self.frames += 1
         return {"tracked": tracked, "redetect": bool(redetect), "live": len(self.feats),
                 "ms": (time.perf_counter() - t0) * 1e3}
+
+
+def redetect_below(target: int, frac: float) -> int:
+    """The live count below which the loop re-detects: live < frac * target
+    exactly when live < this (for integer live)."""
+    return max(0, min(target, math.ceil(frac * target)))
+
+
+class _StreamState:
+    """Device state of one stream: two pyramids (previous and current), this
+    frame's cell winners, and the feature list with its scratch."""
+
+    def __init__(self, width, height, levels, t, n, cell, target, below, device="cuda"):
+        import torch
+        self.w, self.h, self.levels, self.t, self.n, self.cell = width, height, levels, t, n, cell
+        self.target, self.below = target, below
+        self.pyr = [fastgrid.Pyramid(width, height, levels, device) for _ in range(2)]
+        self.grid = fastgrid.Grid(width, height, cell, device)
+        self.feats = torch.zeros((target, 2), dtype=torch.float32, device=device)
+        self.q = torch.zeros((target, 4), dtype=torch.float32, device=device)
+        self.status = torch.zeros(target, dtype=torch.int32, device=device)
+        self.count = torch.zeros(1, dtype=torch.int32, device=device)
+        self.info = torch.zeros(4, dtype=torch.int32, device=device)
+        self.cur = 0            # index of the pyramid the next frame goes into
+        self.frames = 0
+
+
+class MultiFrontend:
+    """The detect-and-track loop of many camera streams, with every feature
+    list resident in device memory.  A step takes one frame from each of any
+    subset of the streams: one batched detection (SAD-A, fast_submit) on the
+    new frames, then one fast_frontend_step that tracks every stream's live
+    features from its previous frame and re-detects where too few remain.
+    The host moves no feature data; info() and features() read a stream's
+    results when asked."""
+
+    def __init__(self, ctx: fastgrid.Context, shapes, targets, redetect_fracs,
+                 mode: int = fastgrid.FAST_TRACK_GAIN | fastgrid.FAST_TRACK_OFFSET, max_iter: int = 30,
+                 eps: float = 0.01, score: int = fastgrid.FAST_SCORE_SADA):
+        self.ctx, self.mode, self.max_iter, self.eps, self.score = ctx, mode, max_iter, eps, score
+        self.streams = [_StreamState(w, h, L, t, n, c, tg, redetect_below(tg, fr))
+                        for (w, h, L, t, n, c), tg, fr in zip(shapes, targets, redetect_fracs)]
+
+    def _job(self, i: int, prev) -> fastgrid.fast_frontend_job:
+        st = self.streams[i]
+        cur = st.pyr[st.cur]
+        P = ctypes.POINTER(fastgrid.fast_plane)
+        return fastgrid.fast_frontend_job(
+            ctypes.cast(prev.planes, P) if prev is not None else None, ctypes.cast(cur.planes, P),
+            st.levels, st.grid.ptr, st.cell, st.target, st.below, st.feats.data_ptr(), st.count.data_ptr(),
+            st.q.data_ptr(), st.status.data_ptr(), st.info.data_ptr())
+
+    def step(self, frames: dict, stream=None) -> int:
+        """frames: {stream index: host uint8 frame (height x >= width)}.
+        Enqueues the step; returns the front-end ticket."""
+        idx = sorted(frames)
+        for i in idx:
+            st = self.streams[i]
+            st.pyr[st.cur].upload(frames[i])
+        det = fastgrid.Context.make_jobs(
+            (self.streams[i].pyr[self.streams[i].cur], self.streams[i].t, self.streams[i].n,
+             self.streams[i].cell, self.streams[i].grid, self.score) for i in idx)
+        self.ctx.submit(det, stream)
+        jobs = (fastgrid.fast_frontend_job * len(idx))()
+        for k, i in enumerate(idx):
+            st = self.streams[i]
+            jobs[k] = self._job(i, st.pyr[1 - st.cur] if st.frames > 0 else None)
+        tk = fastgrid.fast_frontend_step(self.ctx.handle, jobs, len(idx), self.mode, self.max_iter, self.eps,
+                                         stream)
+        for i in idx:
+            st = self.streams[i]
+            st.cur = 1 - st.cur
+            st.frames += 1
+        return tk
+
+    def info(self, i: int) -> tuple:
+        """(tracked, re-detected, live) of stream i's last step."""
+        v = self.streams[i].info.cpu().numpy()
+        return int(v[0]), bool(v[1]), int(v[2])
+
+    def features(self, i: int) -> np.ndarray:
+        """Stream i's live features (level-0 positions in its last frame)."""
+        st = self.streams[i]
+        n = int(st.count.cpu().numpy()[0])
+        return st.feats[:n].cpu().numpy().astype(np.float64)

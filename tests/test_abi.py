@@ -40,6 +40,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(fastgrid.fast_plane) == 24
     assert fastgrid.FEATURE_DTYPE.itemsize == 8
     assert ctypes.sizeof(fastgrid.fast_job) == 40
+    assert ctypes.sizeof(fastgrid.fast_shape_region) == 20
 
 
 def test_pyr_and_grid_dims():

@@ -31,3 +31,11 @@ def test_pick_new_strongest_free_cells_first():
 def test_cell_of():
     xy = np.array([[0.0, 0.0], [31.9, 0.0], [32.0, 0.0], [0.0, 32.0], [100.5, 70.2]])
     assert frontend.cell_of(xy, 32, 5).tolist() == [0, 0, 1, 5, 13]
+
+
+def test_redetect_threshold_matches_float_rule():
+    for target in (1, 7, 60, 100, 150, 1024):
+        for frac in (0.0, 0.1, 0.3, 0.5, 0.9, 0.95, 1.0):
+            below = frontend.redetect_below(target, frac)
+            for live in range(target + 1):
+                assert (live < below) == (live < frac * target), (target, frac, live)
