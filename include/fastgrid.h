@@ -286,7 +286,7 @@ int fast_submit(fast_ctx *ctx, const fast_job *jobs, int njobs, void *stream,
  * without any allocation.  The queue counters, job table and work items go
  * to a fixed scratch array in device memory that the library holds on each
  * device from the first fast_ctx_create there until the process ends
- * (FAST_STATIC_SCRATCH_BYTES, about 334 KiB), through a pinned staging buffer
+ * (FAST_STATIC_SCRATCH_BYTES, about 336 KiB), through a pinned staging buffer
  * the context set up at creation; the call then enqueues the same kernels as
  * fast_submit.  The caller still owns every plane and output.
  * Limits: njobs <= FAST_STATIC_MAX_JOBS and at most FAST_STATIC_MAX_ITEMS
@@ -303,7 +303,7 @@ int fast_submit(fast_ctx *ctx, const fast_job *jobs, int njobs, void *stream,
  * which it never returns. */
 #define FAST_STATIC_MAX_JOBS 256
 #define FAST_STATIC_MAX_ITEMS 32768
-#define FAST_STATIC_SCRATCH_BYTES 342272
+#define FAST_STATIC_SCRATCH_BYTES 344320
 int fast_submit_static(fast_ctx *ctx, const fast_job *jobs, int njobs, void *stream,
                        uint64_t *ticket);
 

@@ -27,6 +27,10 @@ HIPCC_FLAGS = [
     # float2 FMA becoming v_pk_fma_f32 without it and two FMAs with it); the
     # host pass does not know it and warns that it ignores it
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no atomic optimiser: its wave-level rewrite of a one-lane atomic reads
+    # the result right after issuing it, which would put the work queue's
+    # ticket latency on the persistent kernel's critical path
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-fvisibility=hidden",
 ]
 

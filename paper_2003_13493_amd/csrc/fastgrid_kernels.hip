@@ -1297,19 +1297,51 @@ __global__ void __launch_bounds__(512) detect_upper_batch_kernel(const fg_job *_
 }
 
 // Persistent batched detectors.  Work items are regions of all jobs (items[]
-// gives each one's job and region).  Workgroup g starts with items g and
-// g + G (G blocks, at most `total`); the rest are handed out by an atomic
-// counter, ticket k being item 2G + k, re-armed by the last workgroup out.
+// gives each one's job and region), split over FG_QUEUES queues: queue c
+// hands out items c, c + 8, c + 16, ..., so every queue holds an even share of
+// the list (whole regions first, clipped ones last).  Workgroup g uses queue
+// g % 8; it starts with that queue's positions g / 8 and g / 8 + n (n
+// workgroups on the queue) and then takes position 2n + k for its k-th ticket
+// of the queue's counter.  Eight heads on separate cache lines keep the
+// tickets from queueing behind each other.
+struct Queue {
+    unsigned *head;
+    int c, n, first;    // queue index, its workgroups, this workgroup's first position
+};
 
-// The last workgroup out re-arms the queue for the next launch (every ticket
+__device__ __forceinline__ Queue queue_of(unsigned *counter) {
+    Queue q;
+    const int G = (int)gridDim.x;
+    q.c = (int)(blockIdx.x % FG_QUEUES);
+    q.first = (int)(blockIdx.x / FG_QUEUES);
+    q.n = (G - q.c + FG_QUEUES - 1) / FG_QUEUES;
+    q.head = counter + q.c * FG_QUEUE_STRIDE;
+    return q;
+}
+
+// Item at queue position pos, or total past the end.
+__device__ __forceinline__ int queue_item(const Queue &q, long long pos, int total) {
+    const long long it = (long long)q.c + (long long)FG_QUEUES * pos;
+    return it < total ? (int)it : total;
+}
+
+// A ticket of the queue.  The ticket's value is first needed after the
+// passes of a whole region, so no wait may follow the atomic at once (the
+// library is built without the atomic optimiser, whose wave-level rewrite
+// reads the result right after the atomic).
+__device__ __forceinline__ unsigned queue_ticket(const Queue &q) {
+    return __hip_atomic_fetch_add(q.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The last workgroup out re-arms the queues for the next launch (every ticket
 // a workgroup drew has been resolved by then).
 __device__ __forceinline__ void queue_exit(unsigned *counter) {
     if (threadIdx.x == 0) {
         __threadfence();
-        const unsigned done = atomicAdd(&counter[1], 1u);
+        const unsigned done = atomicAdd(&counter[FG_EXIT_WORD], 1u);
         if (done == gridDim.x - 1) {
-            atomicExch(&counter[0], 0u);
-            atomicExch(&counter[1], 0u);
+            for (int c = 0; c < FG_QUEUES; ++c) atomicExch(&counter[c * FG_QUEUE_STRIDE], 0u);
+            atomicExch(&counter[FG_EXIT_WORD], 0u);
         }
     }
 }
@@ -1335,9 +1367,13 @@ detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__
     // the two buffers alternate, so a value is never overwritten before every
     // wave has read it.
     __shared__ int s_next[2];
-    const int G = (int)gridDim.x;
-    int item = (int)blockIdx.x;
-    int next = item + G < total ? item + G : total;
+    const Queue q = queue_of(counter);
+    int item = queue_item(q, q.first, total);
+    if (item >= total) {   // a queue with fewer items than workgroups
+        queue_exit(counter);
+        return;
+    }
+    int next = queue_item(q, q.first + (long long)q.n, total);
     fg_item il = items[item];
     fg_item in = next < total ? items[next] : fg_item{0u, 0u};
     TileRegs T;
@@ -1364,7 +1400,7 @@ detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__
         describe_fused(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1, st, g0, g1, g2);
         __syncthreads();   // [B]
         unsigned ticket = 0;
-        if (threadIdx.x == 0 && next < total) ticket = atomicAdd(&counter[0], 1u);
+        if (threadIdx.x == 0 && next < total) ticket = queue_ticket(q);
         int after = total;
         // the staged geometry depends only on the fused level count and the
         // region's size once its origin is 16-aligned across and 4-aligned down
@@ -1374,10 +1410,7 @@ detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__
         run_passes(
             smem, g0, g1, g2, fused_levels(J), R.P, keys, &gcache, gkey,
             [&]() {
-                if (threadIdx.x == 0) {
-                    const unsigned cand = 2u * (unsigned)G + ticket;
-                    s_next[b] = next < total && cand < (unsigned)total ? (int)cand : total;
-                }
+                if (threadIdx.x == 0) s_next[b] = next < total ? queue_item(q, 2LL * q.n + ticket, total) : total;
             },
             [&]() {   // after [C]
                 after = __builtin_amdgcn_readfirstlane(s_next[b]);
@@ -1412,16 +1445,13 @@ __global__ void __launch_bounds__(512) detect_batch_generic_kernel(const fg_job 
                                                                    int total, unsigned *counter) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     __shared__ int s_item;
-    const int G = (int)gridDim.x;
+    const Queue q = queue_of(counter);
     for (int k = 0;; ++k) {
         __syncthreads();   // every wave has read the previous s_item
         if (threadIdx.x == 0) {
-            int it = (int)blockIdx.x + k * G;
-            if (k >= 2) {
-                const unsigned t = atomicAdd(&counter[0], 1u);
-                it = 2 * G + (int)min(t, (unsigned)total);
-            }
-            s_item = it < total ? it : total;
+            long long pos = q.first + (long long)k * q.n;
+            if (k >= 2) pos = 2LL * q.n + queue_ticket(q);
+            s_item = queue_item(q, pos, total);
         }
         __syncthreads();
         const int item = s_item;

@@ -77,7 +77,7 @@ struct Retired {
 // reaches it only through the address hipGetSymbolAddress returns for that
 // device (the array's name is a host-side stand-in, not a device address).
 namespace {
-constexpr size_t STATIC_COUNTER_BYTES = 256;   // FG_COUNTER_WORDS words, padded
+constexpr size_t STATIC_COUNTER_BYTES = 2304;   // FG_COUNTER_WORDS words
 constexpr size_t static_items_offset(int njobs) { return STATIC_COUNTER_BYTES + ((sizeof(fg_job) * (size_t)njobs + 15) & ~(size_t)15); }
 constexpr size_t STATIC_BYTES = static_items_offset(FAST_STATIC_MAX_JOBS) + sizeof(fg_item) * FAST_STATIC_MAX_ITEMS;
 static_assert(FG_COUNTER_WORDS * sizeof(unsigned) <= STATIC_COUNTER_BYTES, "counter words fit their slot");

@@ -89,9 +89,15 @@ hipError_t fg_launch_score_maps(const fg_job &j, const fg_launch &L, hipStream_t
 // from j.smap (j.lvl unused) into j.out.
 hipError_t fg_launch_nms_grid(const fg_job &j, int radius, hipStream_t s);
 
-// Words of the persistent batched kernel's counter buffer: the queue head and
-// the exit count (the rest is padding).
-constexpr int FG_COUNTER_WORDS = 16;
+// The persistent batched kernels' counter buffer: FG_QUEUES work queues, the
+// head of queue c at word FG_QUEUE_STRIDE * c, and the exit count at word
+// FG_QUEUES * FG_QUEUE_STRIDE.  The heads sit 256 bytes apart, on separate
+// cache lines: one shared head serialises every ticket of a launch (about
+// 13 ns each on MI355X, which alone bounded the 64-frame batch near 100 us).
+constexpr int FG_QUEUES = 8;
+constexpr int FG_QUEUE_STRIDE = 64;
+constexpr int FG_EXIT_WORD = FG_QUEUES * FG_QUEUE_STRIDE;
+constexpr int FG_COUNTER_WORDS = FG_EXIT_WORD + FG_QUEUE_STRIDE;
 
 // One work item of the batched kernel: a region of a job.
 struct fg_item {
