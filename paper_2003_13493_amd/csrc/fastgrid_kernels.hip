@@ -1297,13 +1297,19 @@ __global__ void __launch_bounds__(512) detect_upper_batch_kernel(const fg_job *_
 }
 
 // Persistent batched detectors.  Work items are regions of all jobs (items[]
-// gives each one's job and region), split over FG_QUEUES queues: queue c
-// hands out items c, c + 8, c + 16, ..., so every queue holds an even share of
-// the list (whole regions first, clipped ones last).  Workgroup g uses queue
-// g % 8; it starts with that queue's positions g / 8 and g / 8 + n (n
-// workgroups on the queue) and then takes position 2n + k for its k-th ticket
-// of the queue's counter.  Eight heads on separate cache lines keep the
-// tickets from queueing behind each other.
+// gives each one's job and region, row by row within a job, whole regions
+// first and clipped ones last), split over FG_QUEUES queues.  The list is
+// cut into runs of FG_QUEUE_RUN consecutive items dealt round-robin: queue c
+// holds runs c, c + 8, c + 16, ... and then, past the last full round of
+// runs, items c, c + 8, ... of the remainder, so the queues stay within one
+// run of each other.  Workgroup g uses queue g % 8; it starts with that
+// queue's positions g / 8 and g / 8 + n (n workgroups on the queue) and then
+// takes position 2n + k for its k-th ticket of the queue's counter.  Eight
+// heads on separate cache lines keep the tickets from queueing behind each
+// other.  Workgroups are placed on the XCDs round-robin, so one queue's
+// workgroups share one XCD and its L2: a run's regions lie side by side in
+// their frame and share the cache lines of their tiles, which a run of one
+// region (neighbours on eight different L2s) fetches again from memory.
 struct Queue {
     unsigned *head;
     int c, n, first;    // queue index, its workgroups, this workgroup's first position
@@ -1321,7 +1327,11 @@ __device__ __forceinline__ Queue queue_of(unsigned *counter) {
 
 // Item at queue position pos, or total past the end.
 __device__ __forceinline__ int queue_item(const Queue &q, long long pos, int total) {
-    const long long it = (long long)q.c + (long long)FG_QUEUES * pos;
+    const long long runs = total / (FG_QUEUES * FG_QUEUE_RUN);   // full rounds of runs
+    const long long in_runs = runs * FG_QUEUE_RUN;               // positions per queue inside them
+    const long long it = pos < in_runs
+                             ? ((pos / FG_QUEUE_RUN) * FG_QUEUES + q.c) * FG_QUEUE_RUN + pos % FG_QUEUE_RUN
+                             : in_runs * FG_QUEUES + q.c + (long long)FG_QUEUES * (pos - in_runs);
     return it < total ? (int)it : total;
 }
 

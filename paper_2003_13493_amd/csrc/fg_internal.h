@@ -98,6 +98,11 @@ constexpr int FG_QUEUES = 8;
 constexpr int FG_QUEUE_STRIDE = 64;
 constexpr int FG_EXIT_WORD = FG_QUEUES * FG_QUEUE_STRIDE;
 constexpr int FG_COUNTER_WORDS = FG_EXIT_WORD + FG_QUEUE_STRIDE;
+// Consecutive work items a queue hands out before the next queue's run: 16
+// neighbouring 64x64 regions on one XCD cut the batch's fetched bytes 3x
+// against runs of one; runs of 64 cut them further but leave the queues
+// (and XCDs) finishing up to 2% apart.
+constexpr int FG_QUEUE_RUN = 16;
 
 // One work item of the batched kernel: a region of a job.
 struct fg_item {

@@ -2,7 +2,7 @@
 
     python -m paper_2003_13493_amd.profile_tools trace    <kernel_stats.csv> [out.md "command"]
     python -m paper_2003_13493_amd.profile_tools traffic  <fetch_dir> <write_dir> <copy_bytes> [out.json "cmd" ...]
-    python -m paper_2003_13493_amd.profile_tools counters <pmc_dir> [out.md "command"]
+    python -m paper_2003_13493_amd.profile_tools counters <pmc_dir> [out.md "command" ...]
 
 `traffic` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch, two separate
 --pmc runs) of the batched detect kernel into HBM bytes per launch.  Each
@@ -72,7 +72,8 @@ DETECT_SOURCES = ("fastgrid_kernels.hip", "fg_internal.h", "fastgrid_runtime.hip
 
 def kernel_source_hash(names=DETECT_SOURCES) -> str:
     """sha256[:16] of kernel and runtime sources with comments and blank space
-    removed, so that a record stays valid across comment-only edits."""
+    removed, so that a record stays valid across comment-only edits, and of
+    the hipcc flags the library is built with."""
     import hashlib
     import re
     if isinstance(names, str):
@@ -85,6 +86,8 @@ def kernel_source_hash(names=DETECT_SOURCES) -> str:
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         text = re.sub(r"//[^\n]*", "", text)
         parts.append("\n".join(line.strip() for line in text.splitlines() if line.strip()))
+    from .build import HIPCC_FLAGS
+    parts.append(" ".join(HIPCC_FLAGS))
     return hashlib.sha256("\n".join(parts).encode()).hexdigest()[:16]
 
 
@@ -108,7 +111,7 @@ def trace_md(stats_csv: str, command: str) -> str:
         f"Summary: `python -m paper_2003_13493_amd.profile_tools trace {stats_csv}`.",
         "detect_batch_kernel is one persistent launch over the whole 64-frame batch (pyramid levels 1-2",
         "are built inside it); detect_plain_kernel is the plain path, one launch per frame.",
-        f"Kernel source hash (sha256[:16] of the kernel and runtime sources without comments) = {kernel_source_hash()}.", "", *lines, ""])
+        f"Kernel source hash (sha256[:16] of the kernel and runtime sources without comments, and the hipcc flags) = {kernel_source_hash()}.", "", *lines, ""])
 
 
 def counters(pmc_dir: str, name_part: str = "detect_batch_kernel") -> dict:
@@ -134,7 +137,7 @@ def track_md(trace_csv: str, command: str) -> str:
              f"Summary: `python -m paper_2003_13493_amd.profile_tools track {trace_csv}`.",
              "track_kernel is one launch per call, one wave64 per feature; the frames are two 752x480 crops of one",
              "synthetic scene moved by (3, -2), 3 levels, max 30 iterations per level, eps 0.01.",
-             f"Kernel source hash (sha256[:16] of the kernel and runtime sources without comments) = {track_source_hash()}.", "",
+             f"Kernel source hash (sha256[:16] of the kernel and runtime sources without comments, and the hipcc flags) = {track_source_hash()}.", "",
              "| parameters | features | calls | average ns | min ns | max ns |", "|---|---|---|---|---|---|"]
     i = 0
     for mode in TRACK_MODES:
@@ -167,7 +170,7 @@ def track_counters_md(pmc_dir: str, command: str) -> str:
              f"Summary: `python -m paper_2003_13493_amd.profile_tools track-counters {pmc_dir}`.",
              "Medians over each configuration's timed dispatches, per wave (one wave is one feature).",
              "wait = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES; VALU active = SQ_ACTIVE_INST_VALU / SQ_WAVE_CYCLES.",
-             f"Kernel source hash (sha256[:16] of the kernel and runtime sources without comments) = {track_source_hash()}.", "",
+             f"Kernel source hash (sha256[:16] of the kernel and runtime sources without comments, and the hipcc flags) = {track_source_hash()}.", "",
              "| parameters | features | VALU instr / wave | SALU instr / wave | VMEM instr / wave | "
              "wave cycles / wave | wait | VALU active |", "|---|---|---|---|---|---|---|---|"]
     i = 0
@@ -229,7 +232,11 @@ if __name__ == "__main__":
             lines += [f"| {k} | {v:.0f} |" for k, v in rec.items()]
             with open(sys.argv[3], "w") as f:
                 f.write("\n".join(["# SQ counters: batched detect kernel on the 64-frame batch", "",
-                                    "Command (repo root):", "", "    " + sys.argv[4], "",
-                                    f"Kernel source hash (sha256[:16] of the kernel and runtime sources without comments) = {kernel_source_hash()}.", "",
+                                    "Commands (repo root), one run per counter set:", "",
+                                    *["    " + c for c in sys.argv[4:]], "",
+                                    f"Summary: `python -m paper_2003_13493_amd.profile_tools counters {sys.argv[2]}` "
+                                    "(median over the runs' dispatches of the batched kernel; whole-device totals "
+                                    "per dispatch).", "",
+                                    f"Kernel source hash (sha256[:16] of the kernel and runtime sources without comments, and the hipcc flags) = {kernel_source_hash()}.", "",
                                     *lines, ""]))
         print(json.dumps(rec, indent=1))
