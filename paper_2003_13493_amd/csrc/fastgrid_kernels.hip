@@ -147,15 +147,27 @@ __device__ __forceinline__ int wave_scan(int x) {
     return x;
 }
 
-// Bit i of the result is set iff bits i..i+n-1 of m are all set (n >= 1).
+// Bit i of the result is set iff bits i..i+n-1 of m are all set (1 <= n <=
+// 16): runs of 2, 4, 8, 16 by doubling while they fit in n, then the
+// remainder.  The shift amounts depend on n only (uniform, so they are scalar
+// and hoisted out of the callers' loops); a step that does not apply shifts by
+// 0, so the code has no branches.
 __device__ __forceinline__ uint32_t runs(uint32_t m, int n) {
-    int have = 1;
-    while (have * 2 <= n) {
-        m &= m >> have;
-        have *= 2;
-    }
-    if (have < n) m &= m >> (n - have);
-    return m;
+    const int s1 = n >= 2 ? 1 : 0, s2 = n >= 4 ? 2 : 0, s4 = n >= 8 ? 4 : 0, s8 = n >= 16 ? 8 : 0;
+    m &= m >> s1;
+    m &= m >> s2;
+    m &= m >> s4;
+    m &= m >> s8;
+    return m & (m >> (n - 1 - s1 - s2 - s4 - s8));
+}
+
+// The same for n <= 8.
+__device__ __forceinline__ uint32_t runs8(uint32_t m, int n) {
+    const int s1 = n >= 2 ? 1 : 0, s2 = n >= 4 ? 2 : 0, s4 = n >= 8 ? 4 : 0;
+    m &= m >> s1;
+    m &= m >> s2;
+    m &= m >> s4;
+    return m & (m >> (n - 1 - s1 - s2 - s4));
 }
 
 // Compass test of two pixels in packed 16-bit lanes; per lane >= 0 iff the
@@ -186,6 +198,8 @@ __device__ __forceinline__ s16x2 compass(s16x2 C, s16x2 N, s16x2 E, s16x2 S, s16
 
 // Circle of radius 3 (Section II-D) in cyclic order, as LDS byte offsets.
 #define CIRC(j) (CDY[j] * LP + CDX[j])
+// Offset of a pixel from the top-left corner of its circle's bounding box.
+constexpr int CORNER = 3 * LP + 3;
 constexpr int CDX[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
 constexpr int CDY[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
 
@@ -260,14 +274,17 @@ __device__ __forceinline__ int max_threshold(const uint32_t (&v)[16], uint32_t c
 // unsigned subtraction.
 template <int KIND>
 __device__ __forceinline__ uint32_t full_score(const uint8_t *p, int t, int n) {
-    const uint32_t cv = p[0];
+    // every read is at a non-negative constant offset from the circle's
+    // top-left corner, so all 17 share one address register
+    const uint8_t *q = p - CORNER;
+    const uint32_t cv = q[CORNER];
     const uint32_t hi = cv + (uint32_t)t;
     const uint32_t lo = (int)cv - t > 0 ? cv - (uint32_t)t : 0u;   // darker needs v < c-t; none if c-t <= 0
     uint32_t v[16];
     uint32_t bm = 0, dm = 0, sb = 0, sd = 0;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        v[j] = p[CIRC(j)];
+        v[j] = q[CORNER + CIRC(j)];
         bm = __builtin_amdgcn_alignbit(bm, hi - v[j], 31);   // sign: v > c+t; point j at bit 15-j
         dm = __builtin_amdgcn_alignbit(dm, v[j] - lo, 31);   // sign: v < c-t
         if constexpr (KIND == FAST_SCORE_SADB) {
@@ -545,33 +562,38 @@ __device__ __forceinline__ void group_cache_fill(GroupCache &c, const Seg &s0, c
 }
 static_assert(MAX_GROUPS <= 4 * 256, "four compass rounds per wave with four or more waves");
 
-// P3: keep entries that pass the 8-point test, compacted in place.
+// P3: keep entries that pass the 8-point test, compacted in place.  A lane
+// past the end reads a stale slot (the list has a spare slot per lane beyond
+// its capacity, and n1 <= capacity), tests the pixel at SAFE_OFF instead and
+// is masked off; entries that fail go to the lane's spare slot.  The pass
+// therefore has no branches.
 __device__ int pass_even8(const uint8_t *smem, int t, int k8, uint16_t *list, int n1) {
     const int lane = lane_id();
+    const int spare = list_cap(blockDim.x >> 6) + lane;
     int n2 = 0;
     for (int i0 = 0; i0 < n1; i0 += 64) {
         const int i = i0 + lane;
-        bool pass = false;
-        uint16_t e = NO_ENTRY;
-        if (i < n1) e = list[i];
-        if (e != NO_ENTRY) {
-            const uint8_t *p = smem + (e & 0x3FFF);
-            const int cv = p[0];
-            const int hi = cv + t, lo = cv - t;
-            uint32_t bm = 0, dm = 0;
+        const uint16_t e = list[i];
+        const bool valid = i < n1 && e != NO_ENTRY;
+        const uint8_t *q = smem + (valid ? (e & 0x3FFFu) : SAFE_OFF) - CORNER;
+        const int cv = q[CORNER];
+        const int hi = cv + t, lo = cv - t;
+        uint32_t bm = 0, dm = 0;
 #pragma unroll
-            for (int j = 0; j < 16; j += 2) {
-                const int v = p[CIRC(j)];
-                bm = __builtin_amdgcn_alignbit(bm, (uint32_t)(hi - v), 31);
-                dm = __builtin_amdgcn_alignbit(dm, (uint32_t)(v - lo), 31);
-            }
-            pass = k8 == 0 ||
-                   ((runs(bm | (bm << 8), k8) | runs(dm | (dm << 8), k8)) & 0xFFu) != 0;
+        for (int j = 0; j < 16; j += 2) {
+            const int v = q[CORNER + CIRC(j)];
+            bm = __builtin_amdgcn_alignbit(bm, (uint32_t)(hi - v), 31);
+            dm = __builtin_amdgcn_alignbit(dm, (uint32_t)(v - lo), 31);
         }
+        // bright arcs in bits 0-15, dark arcs in bits 16-31, each 8-point
+        // mask doubled for the circular wrap: a run of k8 <= 8 starting at
+        // bit 0-7 (16-23) stays below bit 15 (31)
+        const uint32_t w = (bm | (dm << 16)) * 0x101u;
+        const bool pass = valid && (k8 == 0 || (runs8(w, k8) & 0x00FF00FFu) != 0);
         const uint64_t bal = __ballot(pass);
         const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        if (pass) list[n2 + rank] = e;
+        list[pass ? n2 + rank : spare] = e;
         n2 += __popcll(bal);
         wave_sync();
     }
