@@ -43,14 +43,18 @@ constexpr int MAX_FUSED = FG_MAX_FUSED;   // levels built in LDS from one load
 
 // All level tiles share one LDS row pitch, so circle offsets are constants.
 // Band A (rows 0..95): level 0 of a fused sub-tile, or the current level of an
-// unfused one.  Band B (rows 96..143): level 1 at byte 8, level 2 at byte 64.
+// unfused one.  Band B (rows 96..143): level 1 at byte 8, level 2 at byte 68.
+// For a sub-tile whose origin is a multiple of 16 pixels, the compass groups
+// of every level then start 4 bytes past a multiple of 8, so the row words
+// around a group are two aligned 8-byte reads (load8<true>).
 constexpr int LP = 112;
 constexpr int T0 = 16;
 constexpr int T1 = 96 * LP + 8;
-constexpr int T2 = 96 * LP + 64;
+constexpr int T2 = 96 * LP + 68;
 constexpr int TILE_BYTES = 144 * LP;
 static_assert(T0 % 16 == 0 && LP % 16 == 0, "16-byte tile stores in band A");
 static_assert(T1 % 8 == 0 && T2 % 4 == 0, "8-byte reads when halving level 1");
+static_assert(LP % 8 == 0 && T0 % 8 == 0 && T1 % 8 == 0 && T2 % 8 == 4, "aligned compass row reads");
 static_assert(TILE_BYTES <= 16384, "entries hold 14-bit LDS offsets");
 // Score maps: a level's sub-tile area plus a 1-pixel ring.
 constexpr int M0_ROWS = SUB + 2, M0_P = SUB + 4;
@@ -372,6 +376,7 @@ constexpr uint32_t NO_GROUP = 0xFFFFu;
 // Any offset whose 8 pixels and compass points lie inside the tile; a lane
 // with no group reads there and discards the result.
 constexpr uint32_t SAFE_OFF = T0 + 3 * LP + 4;
+static_assert(SAFE_OFF % 8 == 4, "aligned compass row reads at SAFE_OFF");
 
 struct GroupSeq {
     int b1, b2, total;   // first group of level 1, of level 2; group count
@@ -411,17 +416,29 @@ struct GroupCache {
 
 // The words a compass test of 8 pixels reads: the 16 bytes around the group
 // on its own row (4 before, 4 after) and 8 bytes three rows above and below.
+// With A8 every group starts 4 bytes past a multiple of 8 (see the tile
+// layout), and the row is read as two aligned 8-byte words.
 struct Px8 {
     uint32_t D0, D1, D2, D3, N0, N1, S0, S1;
 };
 
+template <bool A8>
 __device__ __forceinline__ Px8 load8(const uint8_t *smem, uint32_t off) {
     const uint8_t *p = smem + off;
     Px8 x;
-    x.D0 = *(const uint32_t *)(p - 4);
-    x.D1 = *(const uint32_t *)(p);
-    x.D2 = *(const uint32_t *)(p + 4);
-    x.D3 = *(const uint32_t *)(p + 8);
+    if constexpr (A8) {
+        const u32x2 lo = *(const u32x2 *)__builtin_assume_aligned(p - 4, 8);
+        const u32x2 hi = *(const u32x2 *)__builtin_assume_aligned(p + 4, 8);
+        x.D0 = lo.x;
+        x.D1 = lo.y;
+        x.D2 = hi.x;
+        x.D3 = hi.y;
+    } else {
+        x.D0 = *(const uint32_t *)(p - 4);
+        x.D1 = *(const uint32_t *)(p);
+        x.D2 = *(const uint32_t *)(p + 4);
+        x.D3 = *(const uint32_t *)(p + 8);
+    }
     x.N0 = *(const uint32_t *)(p - 3 * LP);
     x.N1 = *(const uint32_t *)(p - 3 * LP + 4);
     x.S0 = *(const uint32_t *)(p + 3 * LP);
@@ -473,7 +490,7 @@ __device__ __forceinline__ uint32_t bit_range(int lo, int hi) { return (1u << hi
 // is (level << 14) | LDS offset of the pixel.  Returns the wave's pixel count.
 // With `cached` (four or more waves), the group entries are e01 and e23
 // (GroupCache).
-template <int K>
+template <int K, bool A8>
 __device__ int collect(const uint8_t *smem, const Seg &s0, const Seg &s1, const Seg &s2, int t,
                        bool cached, uint32_t e01, uint32_t e23, uint32_t *blist, uint16_t *list) {
     const int lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nwaves = blockDim.x >> 6;
@@ -504,11 +521,11 @@ __device__ int collect(const uint8_t *smem, const Seg &s0, const Seg &s1, const 
             ea = group_entry(s0, s1, s2, q, i0 + lane);
             eb = group_entry(s0, s1, s2, q, i0 + stride + lane);
         }
-        const Px8 xa = load8(smem, entry_off(ea));
+        const Px8 xa = load8<A8>(smem, entry_off(ea));
         if (i0 + stride < q.total) {
             // two rounds: both rounds' LDS reads are issued before either is
             // evaluated
-            const Px8 xb = load8(smem, entry_off(eb));
+            const Px8 xb = load8<A8>(smem, entry_off(eb));
             const uint32_t sva = compass8<K>(xa, T1) & (0u - (uint32_t)(ea != NO_GROUP));
             const uint32_t svb = compass8<K>(xb, T1) & (0u - (uint32_t)(eb != NO_GROUP));
             push(ea, sva);
@@ -678,14 +695,24 @@ __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Ge
         cache->key = cache_key;
     }
     const uint32_t ce01 = cache ? cache->e01 : 0u, ce23 = cache ? cache->e23 : 0u;
+    // every level's groups start 4 bytes past a multiple of 8 (uniform)
+    const bool a8 = ((s0.tbase + s0.gc0) & 7) == 4 && (!s1.n || ((s1.tbase + s1.gc0) & 7) == 4) &&
+                    (!s2.n || ((s2.tbase + s2.gc0) & 7) == 4);
     int n1 = 0;
-    switch (P.kc) {
-        case 0: n1 = collect<0>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
-        case 1: n1 = collect<1>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
-        case 2: n1 = collect<2>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
-        case 3: n1 = collect<3>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
-        default: n1 = collect<4>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
-    }
+    auto run_collect = [&](auto aligned) {
+        constexpr bool A = decltype(aligned)::value;
+        switch (P.kc) {
+            case 0: n1 = collect<0, A>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
+            case 1: n1 = collect<1, A>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
+            case 2: n1 = collect<2, A>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
+            case 3: n1 = collect<3, A>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
+            default: n1 = collect<4, A>(smem, s0, s1, s2, P.t, cache != nullptr, ce01, ce23, blist, list); break;
+        }
+    };
+    if (a8)
+        run_collect(std::true_type());
+    else
+        run_collect(std::false_type());
     wave_sync();
     // the later passes run at a raised wave priority: a wave that is further
     // through its sub-tile issues first, so workgroups reach their barriers
