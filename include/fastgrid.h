@@ -86,8 +86,8 @@ typedef struct {
     uint8_t reserved;
 } fast_feature;
 
-/* Corner score kinds (Section II-D names three, and each is 0 where the
- * segment test fails):
+/* Corner score kinds (Section II-D names three; a pixel that is not a corner
+ * by the segment test scores 0 under all of them):
  *   FAST_SCORE_SADB  max(sum over brighter circle points of (p-c-t),
  *                        sum over darker circle points of (c-p-t)), the default;
  *   FAST_SCORE_SADA  the same two sums over only the circle points that lie on

@@ -123,7 +123,7 @@ static int on_arc(uint32_t mask16, int n, int i) {
  * which the point is still a corner).
  * READING, SAD-A: the thresholded sum of fastref_score_at restricted to the
  *   circle points that lie on a qualifying arc (a run of at least n points of
- *   one label), max over the two labels; 0 if the segment test fails.
+ *   one label), max over the two labels; 0 for a pixel that is not a corner.
  * READING, MT: d = the largest value such that some n consecutive circle points
  *   all differ from the centre by at least d in the same direction
  *   (brighter: p - c, darker: c - p).  The segment test with threshold t'
