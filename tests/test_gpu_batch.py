@@ -173,6 +173,34 @@ def test_batch_single_subtile_regions_of_mixed_sides(ctx):
         check_all(specs, pyrs, grids, want, f"mixed sides round {r}")
 
 
+@pytest.mark.parametrize("nframes", [1, 9, 127, 128, 129, 255, 300])
+def test_batch_region_counts_around_queue_runs(ctx, nframes):
+    """The work queues hand out runs of 16 consecutive regions round-robin
+    over 8 queues, then deal the remainder past the last full round of 128
+    item by item.  Batches of 64x64 frames (one region each) with region
+    counts below, at and around multiples of 128 must still have every region
+    processed exactly once: every frame matches the oracle."""
+    specs, frames, want = [], [], []
+    for i in range(nframes):
+        levels = 1 + i % 3
+        s = synth.FrameSpec(64, 64, levels, synth.BATCH_T[i % 4], synth.BATCH_N[i % 3], (16, 32, 64)[i % 3],
+                            seed=5000 + i, nshapes=12, sigma=4.0)
+        img = s.make()
+        specs.append(s)
+        frames.append(img)
+        slots, planes = oracle.detect_grid(img, 64, levels, s.t, s.n, s.cell)
+        want.append((slots, [p[:, :pw].copy() for p, pw in planes]))
+    print(f"case batch of {nframes} one-region frames", flush=True)
+    pyrs, grids, jobs = make_resident(specs, frames)
+    for r in range(2):
+        for g in grids:
+            g.tensor.fill_(0x5A)
+        torch.cuda.synchronize()
+        tk = ctx.submit(jobs)
+        assert ctx.wait(tk, 60_000)
+        check_all(specs, pyrs, grids, want, f"{nframes} frames round {r}")
+
+
 def test_submit_grows_its_staging_buffer(ctx):
     """Two 4096x2160 frames with 16-pixel regions are about 69,000 work items,
     more than a submission slot first holds: the job table and items move to
