@@ -695,7 +695,9 @@ __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Ge
         cache->key = cache_key;
     }
     const uint32_t ce01 = cache ? cache->e01 : 0u, ce23 = cache ? cache->e23 : 0u;
-    // every level's groups start 4 bytes past a multiple of 8 (uniform)
+    // every level's groups start 4 bytes past a multiple of 8 (uniform): true
+    // for fused sub-tiles, whose origins are on the 16-pixel grid; the single
+    // deeper levels of process_subtile_upper may start elsewhere
     const bool a8 = ((s0.tbase + s0.gc0) & 7) == 4 && (!s1.n || ((s1.tbase + s1.gc0) & 7) == 4) &&
                     (!s2.n || ((s2.tbase + s2.gc0) & 7) == 4);
     int n1 = 0;
