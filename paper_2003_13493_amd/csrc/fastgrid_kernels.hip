@@ -58,8 +58,9 @@ static_assert(LP % 8 == 0 && T0 % 8 == 0 && T1 % 8 == 0 && T2 % 8 == 4, "aligned
 static_assert(TILE_BYTES <= 16384, "entries hold 14-bit LDS offsets");
 // Score maps: a level's sub-tile area plus a 1-pixel ring.
 constexpr int M0_ROWS = SUB + 2, M0_P = SUB + 4;
-constexpr int M1_ROWS = SUB / 2 + 2, M1_P = SUB / 2 + 4;
-constexpr int M2_ROWS = SUB / 4 + 2, M2_P = SUB / 4 + 4;
+constexpr int M1_ROWS = SUB / 2 + 2, M1_P = M0_P;
+constexpr int M2_ROWS = SUB / 4 + 2, M2_P = M0_P;
+constexpr int MP = M0_P;   // one pitch for every level's score map
 constexpr int MAX_RCELLS = 16;
 constexpr int MAX_KEYS = MAX_RCELLS * MAX_RCELLS;
 // Groups of 8 pixels scored per sub-tile, at most: every level's area plus a
@@ -68,9 +69,12 @@ constexpr int MAX_GROUPS = 66 * 9 + 34 * 5 + 18 * 3;
 constexpr uint16_t NO_ENTRY = 0xFFFF;
 
 constexpr int OFF_M0 = TILE_BYTES;
-constexpr int OFF_M1 = OFF_M0 + M0_ROWS * M0_P * 2;
-constexpr int OFF_M2 = OFF_M1 + M1_ROWS * M1_P * 2;
-constexpr int OFF_KEYS = (OFF_M2 + M2_ROWS * M2_P * 2 + 15) & ~15;
+// levels 1 and 2 share a band of M1_ROWS rows: level 1 in columns 0..35,
+// level 2 in columns 40..59
+constexpr int OFF_M1 = OFF_M0 + M0_ROWS * MP * 2;
+constexpr int OFF_M2 = OFF_M1 + 40 * 2;
+constexpr int OFF_KEYS = (OFF_M1 + M1_ROWS * MP * 2 + 15) & ~15;
+static_assert(SUB / 2 + 4 <= 40 && 40 + SUB / 4 + 4 <= MP && M2_ROWS <= M1_ROWS, "level 1 and 2 maps share a band");
 constexpr int OFF_KEYS2 = OFF_KEYS + MAX_KEYS * 4;   // second buffer for the pipelined kernel
 constexpr int OFF_WAVES = OFF_KEYS2 + MAX_KEYS * 4;
 static_assert(OFF_WAVES % 16 == 0, "aligned scratch");
@@ -96,6 +100,7 @@ namespace {
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 // Image planes and outputs reach the kernels as generic pointers inside job
 // structs.  Accessing them through global-address-space pointers makes the
@@ -291,10 +296,20 @@ __device__ __forceinline__ uint32_t full_score(const uint8_t *p, int t, int n) {
         v[j] = q[CORNER + CIRC(j)];
         bm = __builtin_amdgcn_alignbit(bm, hi - v[j], 31);   // sign: v > c+t; point j at bit 15-j
         dm = __builtin_amdgcn_alignbit(dm, v[j] - lo, 31);   // sign: v < c-t
-        if constexpr (KIND == FAST_SCORE_SADB) {
-            sb += __builtin_elementwise_sub_sat(v[j], hi);
-            sd += __builtin_elementwise_sub_sat(lo, v[j]);
+    }
+    if constexpr (KIND == FAST_SCORE_SADB) {
+        // the sums in 16-bit lanes, points j and j+8 side by side: each lane
+        // sums 8 terms of at most 255, so nothing saturates but the terms
+        const u16x2 hi2 = {(unsigned short)hi, (unsigned short)hi}, lo2 = {(unsigned short)lo, (unsigned short)lo};
+        u16x2 b2 = {0, 0}, d2 = {0, 0};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const u16x2 p = __builtin_bit_cast(u16x2, v[j] | (v[j + 8] << 16));
+            b2 += __builtin_elementwise_sub_sat(p, hi2);
+            d2 += __builtin_elementwise_sub_sat(lo2, p);
         }
+        sb = (uint32_t)b2.x + b2.y;
+        sd = (uint32_t)d2.x + d2.y;
     }
     const uint32_t b2 = bm | (bm << 16), d2 = dm | (dm << 16);
     const uint32_t rb = runs(b2, n) & 0xFFFFu, rd = runs(d2, n) & 0xFFFFu;
@@ -736,7 +751,7 @@ __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Ge
                 const int l = e >> 14;
                 int row, col;
                 tile_rc(e & 0x3FFF, row, col);
-                maps[row * sel3(l, m0.mp, m1.mp, m2.mp) + col + sel3(l, m0.mbias, m1.mbias, m2.mbias)] =
+                maps[row * MP + col + sel3(l, m0.mbias, m1.mbias, m2.mbias)] =
                     (uint16_t)s;
             }
         }
@@ -765,7 +780,7 @@ __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Ge
         if (row < sel3(l, m0.rlo, m1.rlo, m2.rlo) || row >= sel3(l, m0.rhi, m1.rhi, m2.rhi) ||
             col < sel3(l, m0.clo, m1.clo, m2.clo) || col >= sel3(l, m0.chi, m1.chi, m2.chi))
             continue;   // ring pixel: its own sub-tile suppresses it
-        const int mp = sel3(l, m0.mp, m1.mp, m2.mp);
+        constexpr int mp = MP;
         const uint16_t *q = maps + row * mp + col + sel3(l, m0.mbias, m1.mbias, m2.mbias);
         const uint32_t s = q[0];
         if (s == 0) continue;
