@@ -396,6 +396,8 @@ def measured_traffic():
 def _serve_stats(st: dict) -> dict:
     st = dict(st)
     st.pop("requests")
+    st.pop("slot_of", None)
+    st.pop("served", None)
     for k in ("mpixel_s", "wall_s", "mean_batch"):
         st[k] = round(st[k], 3)
     st["latency_ms"] = {k: (round(v, 4) if v is not None else None) for k, v in st["latency_ms"].items()}
@@ -439,7 +441,8 @@ def serving(ctx, seconds: float, trace_path: str = "") -> dict:
                        "three runs per mode at the nominal rates; a sweep of "
                        f"{sweep_s:g} s runs at {', '.join(f'{x:g}x' for x in SWEEP)} the rates; the "
                        "+upload entries copy every frame host-to-device before detection "
-                       "(PCIe-inclusive)"}
+                       "(PCIe-inclusive); the *_native entries run the same arrivals and batching rule "
+                       "with the serving loop in the library (fast_pump_run), their sweep up to 4x"}
     srv = serve.Server(ctx, specs, pool_frames=4, slots_per_stream=4, max_batch=64, inflight=4)
     res["offered_mpixel_s"] = round(sum(s.width * s.height * s.rate_fps for s in specs) / 1e6, 1)
     traces = {}
@@ -473,6 +476,26 @@ def serving(ctx, seconds: float, trace_path: str = "") -> dict:
         ok = [r["rate_scale"] for r in rows if r["p99_ms"] is not None and r["p99_ms"] <= 1.0]
         sweep[mode] = {"rows": rows, "max_rate_scale_p99_within_1ms": max(ok) if ok else None}
     res["load_sweep"] = sweep
+    # the same arrivals with the loop in the library (fast_pump_run): three
+    # runs per mode at the nominal rates, then the sweep
+    for mode, batched in (("batched_native", True), ("plain_native", False)):
+        srv.run_native(0.3, seed=99, batched=batched)   # warm-up
+        runs = [_serve_stats(srv.run_native(seconds, seed=17 + rep, batched=batched)) for rep in range(3)]
+        p99s = sorted(r["latency_ms"]["p99"] for r in runs)
+        res[mode] = runs[0]
+        res[mode]["p99_ms_over_runs"] = {"min": p99s[0], "median": p99s[1], "max": p99s[2]}
+        res[mode]["p50_ms_over_runs"] = sorted(r["latency_ms"]["p50"] for r in runs)
+        log(f"serving {mode}: p50 {res[mode]['p50_ms_over_runs']} ms, p99 {p99s} ms, "
+            f"{runs[0]['mpixel_s']} Mpx/s, mean batch {runs[0]['mean_batch']}")
+        rows = []
+        for scale in SWEEP + (3.5, 4.0):
+            st = _serve_stats(srv.run_native(sweep_s, seed=31, batched=batched, rate_scale=scale))
+            rows.append({"rate_scale": scale, "offered_mpixel_s": round(res["offered_mpixel_s"] * scale, 1),
+                         "mpixel_s": st["mpixel_s"], "wall_s": st["wall_s"], "mean_batch": st["mean_batch"],
+                         "p50_ms": st["latency_ms"]["p50"], "p99_ms": st["latency_ms"]["p99"]})
+            log(f"serving sweep {mode} x{scale:g}: {st['mpixel_s']} Mpx/s, p99 {st['latency_ms']['p99']} ms")
+        ok = [r["rate_scale"] for r in rows if r["p99_ms"] is not None and r["p99_ms"] <= 1.0]
+        sweep[mode] = {"rows": rows, "max_rate_scale_p99_within_1ms": max(ok) if ok else None}
     srv.close()
     # the detect-and-track loop of every stream inside the serving loop: one
     # frame in flight per stream, feature lists resident on the device

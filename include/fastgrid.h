@@ -379,6 +379,51 @@ int fast_set_shape_table(fast_ctx *ctx, const fast_shape_region *entries, int n)
  * fast_detect_grid would reject. */
 int fast_shape_region_of(fast_ctx *ctx, int width, int height, int levels, int cell, int *region);
 
+/* Native serving loop (not in the paper; the continuous-batching server of
+ * camera streams).  fast_pump_run replays a schedule of frame arrivals by the
+ * host clock and serves them: whenever a launch lane is free, the oldest
+ * arrived frames whose stream has a free result slot form the next launch
+ * (up to max_batch frames through fast_submit when `batched`, else one frame
+ * through fast_detect_grid_score), the results are copied to the slots' host
+ * buffers, and an event marks the launch done.  The loop busy-polls; nothing
+ * crosses to Python until every request is served.
+ *
+ * A stream describes its resident frames and result slots (all memory
+ * caller-owned; device pointers unless noted): */
+typedef struct {
+    int32_t levels, t, n, cell, score;   /* detector parameters (as fast_job) */
+    int32_t pool_frames;                 /* P >= 1 */
+    const fast_plane *pool;              /* host array of P level-0 planes: frame k of the stream
+                                            is pool[k % P] */
+    int32_t slots;                       /* S >= 1: results in flight at once for this stream */
+    const fast_plane *upper;             /* host array of S * (levels-1) planes: slot s builds
+                                            levels 1.. into upper[s*(levels-1) ..] */
+    fast_feature *const *out;            /* host array of S device grids (gw*gh slots each) */
+    void *const *host_out;               /* host array of S pinned host buffers of gw*gh*8 bytes
+                                            that receive each result, or NULL (no copy) */
+} fast_pump_stream;
+
+typedef struct {
+    int32_t stream;      /* index into the streams array */
+    int32_t frame;       /* frame index k (served from pool[k % P]) */
+    double arrival_s;    /* arrival time in seconds after the run starts, non-decreasing */
+} fast_pump_request;
+
+#define FAST_PUMP_MAX_LANES 8
+/* Serve `nreq` requests with `lanes` (1..FAST_PUMP_MAX_LANES) launches in
+ * flight.  Outputs, per request (host arrays of nreq): done_s, the time the
+ * loop saw its launch complete (seconds after the start), and slot_of, the
+ * result slot it used; *nbatches receives the number of launches.  The run
+ * gives up after max_seconds of wall time (FAST_ETIMEDOUT, with every launch
+ * drained).  Errors: FAST_EINVAL for NULL arrays, nreq < 1, a request naming
+ * no stream, decreasing arrivals, lanes or max_batch out of range, or a
+ * stream or slot that fast_submit would reject; FAST_EHIP if a launch fails
+ * (every lane is drained before returning).  Uses the context's job tables
+ * like fast_submit, so no other submission may be in flight on it. */
+int fast_pump_run(fast_ctx *ctx, const fast_pump_stream *streams, int nstreams, const fast_pump_request *reqs,
+                  int nreq, int lanes, int max_batch, int batched, double max_seconds, double *done_s,
+                  int32_t *slot_of, int32_t *nbatches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -927,6 +927,194 @@ FG_API int fast_frontend_step(fast_ctx *c, const fast_frontend_job *jobs, int nj
     return FAST_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Native serving loop: replay arrivals by the host clock, batch the oldest
+// arrived frames whose stream has a free result slot onto free launch lanes,
+// and record when each launch is seen complete.
+
+namespace {
+
+struct PumpLane {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    std::vector<int> reqs;   // requests of the launch in flight
+    bool busy = false;
+};
+
+struct PumpSlots {
+    std::vector<std::vector<fast_plane>> planes;   // per slot: levels planes, [0] set per request
+    std::vector<char> busy;
+    size_t out_bytes = 0;
+};
+
+static_assert(sizeof(fast_pump_stream) == 64 && sizeof(fast_pump_request) == 16, "pump ABI layout");
+
+int pump_check(fast_ctx *c, const fast_pump_stream *streams, int nstreams, const fast_pump_request *reqs,
+               int nreq) {
+    for (int i = 0; i < nstreams; ++i) {
+        const fast_pump_stream &S = streams[i];
+        if (S.levels < 1 || S.levels > FAST_MAX_LEVELS || S.pool_frames < 1 || !S.pool || S.slots < 1 ||
+            S.slots > 4096 || !S.out || (S.levels > 1 && !S.upper))
+            return fail(c, FAST_EINVAL, "pump stream " + std::to_string(i) + " is malformed");
+        for (int k = 0; k < S.slots; ++k)
+            if (!S.out[k] || (S.host_out && !S.host_out[k]))
+                return fail(c, FAST_EINVAL, "pump stream " + std::to_string(i) + " has a NULL slot buffer");
+    }
+    double last = 0.0;
+    for (int r = 0; r < nreq; ++r) {
+        const fast_pump_request &q = reqs[r];
+        if (q.stream < 0 || q.stream >= nstreams || q.frame < 0)
+            return fail(c, FAST_EINVAL, "pump request " + std::to_string(r) + " names no stream or frame");
+        if (!(q.arrival_s >= last) || !(q.arrival_s < 1e9))
+            return fail(c, FAST_EINVAL, "pump arrivals must be finite and non-decreasing");
+        last = q.arrival_s;
+    }
+    return FAST_OK;
+}
+
+}  // namespace
+
+FG_API int fast_pump_run(fast_ctx *c, const fast_pump_stream *streams, int nstreams, const fast_pump_request *reqs,
+                         int nreq, int lanes, int max_batch, int batched, double max_seconds, double *done_s,
+                         int32_t *slot_of, int32_t *nbatches) {
+    if (!c) return FAST_EINVAL;
+    if (!streams || !reqs || !done_s || !slot_of || !nbatches || nstreams < 1 || nreq < 1)
+        return fail(c, FAST_EINVAL, "pump: NULL array, no stream or no request");
+    if (lanes < 1 || lanes > FAST_PUMP_MAX_LANES) return fail(c, FAST_EINVAL, "pump: lanes not in 1..8");
+    if (max_batch < 1 || max_batch > FAST_MAX_JOBS) return fail(c, FAST_EINVAL, "pump: max_batch out of range");
+    if (!(max_seconds > 0.0)) return fail(c, FAST_EINVAL, "pump: max_seconds must be positive");
+    int rc = pump_check(c, streams, nstreams, reqs, nreq);
+    if (rc) return rc;
+    DeviceGuard g(c->device);
+    std::vector<PumpSlots> slots(nstreams);
+    for (int i = 0; i < nstreams; ++i) {
+        const fast_pump_stream &S = streams[i];
+        int gw = 0, gh = 0;
+        if (fast_grid_dims(S.pool[0].width, S.pool[0].height, S.cell, &gw, &gh) != FAST_OK)
+            return fail(c, FAST_EINVAL, "pump stream " + std::to_string(i) + ": bad frame size or cell");
+        slots[i].out_bytes = (size_t)gw * gh * sizeof(fast_feature);
+        slots[i].busy.assign(S.slots, 0);
+        slots[i].planes.resize(S.slots);
+        for (int k = 0; k < S.slots; ++k) {
+            slots[i].planes[k].resize(S.levels);
+            for (int l = 1; l < S.levels; ++l) slots[i].planes[k][l] = S.upper[k * (S.levels - 1) + (l - 1)];
+        }
+    }
+    std::vector<PumpLane> lane(lanes);
+    for (PumpLane &L : lane) {
+        hipError_t e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            rc = hip_fail(c, e, "pump lane setup");
+            break;
+        }
+        L.reqs.reserve(max_batch);
+    }
+    std::vector<std::vector<int>> pending(nstreams);   // per stream, arrived requests in order
+    std::vector<size_t> head(nstreams, 0);
+    std::vector<fast_job> jobs(batched ? max_batch : 1);
+    for (int r = 0; r < nreq; ++r) {
+        done_s[r] = -1.0;
+        slot_of[r] = -1;
+    }
+    int nb = 0, served = 0, next = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    auto now = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+    // the oldest pending request of a stream with a free slot, or -1
+    auto pick = [&]() {
+        int best = -1;
+        double when = 0.0;
+        for (int i = 0; i < nstreams; ++i) {
+            if (head[i] >= pending[i].size()) continue;
+            const std::vector<char> &b = slots[i].busy;
+            if (std::find(b.begin(), b.end(), 0) == b.end()) continue;
+            const double a = reqs[pending[i][head[i]]].arrival_s;
+            if (best < 0 || a < when) {
+                best = i;
+                when = a;
+            }
+        }
+        return best;
+    };
+    while (rc == FAST_OK && served < nreq) {
+        const double t = now();
+        if (t > max_seconds) {
+            rc = fail(c, FAST_ETIMEDOUT, "pump: max_seconds passed with requests unserved");
+            break;
+        }
+        while (next < nreq && reqs[next].arrival_s <= t) {
+            pending[reqs[next].stream].push_back(next);
+            ++next;
+        }
+        for (PumpLane &L : lane) {   // completions
+            if (!L.busy) continue;
+            const hipError_t e = hipEventQuery(L.done);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) {
+                rc = hip_fail(c, e, "pump launch");
+                break;
+            }
+            const double tt = now();
+            for (int r : L.reqs) {
+                done_s[r] = tt;
+                slots[reqs[r].stream].busy[slot_of[r]] = 0;
+            }
+            served += (int)L.reqs.size();
+            L.reqs.clear();
+            L.busy = false;
+        }
+        for (PumpLane &L : lane) {   // launches
+            if (rc != FAST_OK || L.busy) continue;
+            const int limit = batched ? max_batch : 1;
+            int nj = 0;
+            while ((int)L.reqs.size() < limit) {
+                const int i = pick();
+                if (i < 0) break;
+                const int r = pending[i][head[i]++];
+                const fast_pump_stream &S = streams[i];
+                std::vector<char> &b = slots[i].busy;
+                const int k = (int)(std::find(b.begin(), b.end(), 0) - b.begin());
+                b[k] = 1;
+                slot_of[r] = k;
+                std::vector<fast_plane> &pl = slots[i].planes[k];
+                pl[0] = S.pool[reqs[r].frame % S.pool_frames];
+                jobs[nj] = fast_job{pl.data(), S.levels, S.t, S.n, S.cell, S.out[k], S.score};
+                ++nj;
+                L.reqs.push_back(r);
+            }
+            if (nj == 0) break;
+            if (batched) {
+                uint64_t tk = 0;
+                rc = fast_submit(c, jobs.data(), nj, L.stream, &tk);
+            } else {
+                const fast_job &J = jobs[0];
+                rc = fast_detect_grid_score(c, J.pyr, J.levels, J.t, J.n, J.cell, J.score, J.out, L.stream);
+            }
+            for (int q = 0; rc == FAST_OK && q < nj; ++q) {
+                const int r = L.reqs[q];
+                const fast_pump_stream &S = streams[reqs[r].stream];
+                if (!S.host_out) continue;
+                const hipError_t e = hipMemcpyAsync(S.host_out[slot_of[r]], S.out[slot_of[r]],
+                                                    slots[reqs[r].stream].out_bytes, hipMemcpyDeviceToHost, L.stream);
+                if (e != hipSuccess) rc = hip_fail(c, e, "pump result copy");
+            }
+            if (rc == FAST_OK) {
+                const hipError_t e = hipEventRecord(L.done, L.stream);
+                if (e != hipSuccess) rc = hip_fail(c, e, "pump event");
+            }
+            L.busy = true;   // drained below if anything failed
+            ++nb;
+        }
+    }
+    for (PumpLane &L : lane) {
+        if (L.stream) (void)hipStreamSynchronize(L.stream);
+        if (L.done) (void)hipEventDestroy(L.done);
+        if (L.stream) (void)hipStreamDestroy(L.stream);
+    }
+    *nbatches = nb;
+    return rc;
+}
+
 FG_API int fast_poll(fast_ctx *c, uint64_t ticket) {
     if (!c) return FAST_EINVAL;
     DeviceGuard g(c->device);

@@ -34,7 +34,7 @@ EXPORTS = ("fast_ctx_create", "fast_ctx_destroy", "fast_strerror", "fast_last_er
            "fast_detect_grid_score", "fast_score_maps", "fast_nms_grid",
            "fast_submit", "fast_submit_static", "fast_poll", "fast_wait", "fast_plan_create", "fast_plan_launch",
            "fast_plan_destroy", "fast_set_launch", "fast_track", "fast_set_shape_table",
-           "fast_shape_region_of", "fast_frontend_step")
+           "fast_shape_region_of", "fast_frontend_step", "fast_pump_run")
 
 
 class fast_plane(ctypes.Structure):
@@ -64,6 +64,21 @@ class fast_frontend_job(ctypes.Structure):
                 ("capacity", ctypes.c_int32), ("redetect_below", ctypes.c_int32),
                 ("feats", ctypes.c_void_p), ("count", ctypes.c_void_p), ("q", ctypes.c_void_p),
                 ("status", ctypes.c_void_p), ("info", ctypes.c_void_p)]
+
+
+class fast_pump_stream(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("t", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("cell", ctypes.c_int32), ("score", ctypes.c_int32), ("pool_frames", ctypes.c_int32),
+                ("pool", ctypes.POINTER(fast_plane)), ("slots", ctypes.c_int32),
+                ("upper", ctypes.POINTER(fast_plane)), ("out", ctypes.POINTER(ctypes.c_void_p)),
+                ("host_out", ctypes.POINTER(ctypes.c_void_p))]
+
+
+class fast_pump_request(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_int32), ("frame", ctypes.c_int32), ("arrival_s", ctypes.c_double)]
+
+
+FAST_PUMP_MAX_LANES = 8
 
 
 class FastError(RuntimeError):
@@ -114,6 +129,9 @@ def load() -> ctypes.CDLL:
             "fast_shape_region_of": ([vp, i32, i32, i32, i32, ctypes.POINTER(i32)], i32),
             "fast_frontend_step": ([vp, ctypes.POINTER(fast_frontend_job), i32, i32, i32, ctypes.c_float, vp,
                                     u64p], i32),
+            "fast_pump_run": ([vp, ctypes.POINTER(fast_pump_stream), i32, ctypes.POINTER(fast_pump_request), i32,
+                               i32, i32, i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -253,6 +271,20 @@ def fast_frontend_step(ctx, jobs, njobs: int, mode: int, max_iter: int, eps: flo
     _check(ctx, load().fast_frontend_step(ctx, jobs, njobs, mode, max_iter, eps, _stream(stream),
                                           ctypes.byref(tk)), "fast_frontend_step")
     return tk.value
+
+
+def fast_pump_run(ctx, streams, nstreams: int, reqs, nreq: int, lanes: int, max_batch: int, batched: bool,
+                  max_seconds: float):
+    """Serve nreq requests natively; returns (done_s, slot_of, nbatches) with
+    the per-request arrays as numpy."""
+    done = np.zeros(nreq, dtype=np.float64)
+    slot = np.zeros(nreq, dtype=np.int32)
+    nb = ctypes.c_int32()
+    _check(ctx, load().fast_pump_run(ctx, streams, nstreams, reqs, nreq, lanes, max_batch, int(bool(batched)),
+                                     max_seconds, done.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     slot.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(nb)),
+           "fast_pump_run")
+    return done, slot, nb.value
 
 
 def _stream(stream):

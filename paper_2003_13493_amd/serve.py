@@ -494,6 +494,71 @@ class Server:
             "requests": done,
         }
 
+    def run_native(self, duration_s: float, seed: int = 5, batched: bool = True, rate_scale: float = 1.0,
+                   max_seconds: float | None = None) -> dict:
+        """The same arrivals and batching rule as run(), with the loop itself
+        in the library (fast_pump_run): it replays the arrival schedule by the
+        host clock, launches, copies results and polls completions without
+        returning to Python.  Serves the streams resident now (no joins or
+        leaves, no uploads, no front end); frames of other streams are
+        refused.  Returns the same statistics as run(), plus "slot_of" (the
+        result slot each request used), in request order."""
+        if self.upload or self.frontend is not None:
+            raise ValueError("the native loop serves resident frames by detection only")
+        torch = self.torch
+        live = [i for i, st in enumerate(self.streams) if st is not None]
+        index = {i: j for j, i in enumerate(live)}
+        arr = (fastgrid.fast_pump_stream * len(live))()
+        keep = []   # ctypes arrays the descriptors point into
+        for j, i in enumerate(live):
+            st, spec = self.streams[i], self.specs[i]
+            nup = spec.levels - 1
+            pool = (fastgrid.fast_plane * len(st.pool_planes))(*st.pool_planes)
+            upper = (fastgrid.fast_plane * max(1, len(st.slots) * nup))()
+            for k, sl in enumerate(st.slots):
+                for lv in range(nup):
+                    upper[k * nup + lv] = sl.planes[lv + 1]
+            out = (ctypes.c_void_p * len(st.slots))(*[sl.grid.data_ptr() for sl in st.slots])
+            host = (ctypes.c_void_p * len(st.slots))(*[sl.host.data_ptr() for sl in st.slots])
+            keep += [pool, upper, out, host]
+            arr[j] = fastgrid.fast_pump_stream(
+                spec.levels, spec.t, spec.n, spec.cell, 0, len(pool), pool, len(st.slots), upper, out,
+                host if self.download else None)
+        rates = [s.rate_fps * rate_scale for s in self.specs]
+        schedule = poisson_arrivals(rates, duration_s, seed)
+        served = [(t, s, k) for t, s, k in schedule if s in index]
+        refused = collections.Counter(s for _, s, _ in schedule if s not in index)
+        reqs = (fastgrid.fast_pump_request * len(served))(
+            *[fastgrid.fast_pump_request(index[s], k, t) for t, s, k in served])
+        torch.cuda.synchronize()
+        gc_was = gc.isenabled()
+        gc.disable()
+        try:
+            done, slot_of, nb = fastgrid.fast_pump_run(
+                self.ctx.handle, arr, len(live), reqs, len(served), self.inflight, self.max_batch, batched,
+                max_seconds if max_seconds is not None else 3.0 * duration_s + 10.0)
+        finally:
+            if gc_was:
+                gc.enable()
+        lat_ms = [(d - t) * 1e3 for d, (t, _, _) in zip(done, served)]
+        per_res = collections.defaultdict(list)
+        for (t, s, _), l in zip(served, lat_ms):
+            per_res[f"{self.specs[s].width}x{self.specs[s].height}"].append(l)
+        wall = float(done.max()) if len(done) else 0.0
+        px = sum(self.specs[s].width * self.specs[s].height for _, s, _ in served)
+        return {
+            "mode": ("batched" if batched else "plain") + "-native", "rate_scale": rate_scale,
+            "frames": len(served), "offered_frames": len(schedule), "refused_frames": sum(refused.values()),
+            "refused_by_stream": dict(refused), "duration_s": duration_s,
+            "wall_s": wall, "mpixel_s": px / wall / 1e6 if wall > 0 else 0.0,
+            "latency_ms": percentiles(lat_ms),
+            "latency_ms_by_resolution": {k: percentiles(v) for k, v in sorted(per_res.items())},
+            "batches": nb, "mean_batch": len(served) / nb if nb else 0.0,
+            "streams_admitted": len(live), "streams_waiting": len(self.waiting),
+            "streams_rejected": len(self.waiting), "resident_bytes": self.used, "hbm_budget": self.hbm_budget,
+            "requests": [], "slot_of": slot_of, "served": served,
+        }
+
     def _frontend_batch(self, group, lane, hs) -> int:
         """One batch of the detect-and-track loop: detection (SAD-A) of every
         request's frame into its stream's current pyramid, then the front-end

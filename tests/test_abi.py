@@ -41,6 +41,8 @@ def test_struct_layouts():
     assert fastgrid.FEATURE_DTYPE.itemsize == 8
     assert ctypes.sizeof(fastgrid.fast_job) == 40
     assert ctypes.sizeof(fastgrid.fast_shape_region) == 20
+    assert ctypes.sizeof(fastgrid.fast_pump_stream) == 64
+    assert ctypes.sizeof(fastgrid.fast_pump_request) == 16
 
 
 def test_pyr_and_grid_dims():

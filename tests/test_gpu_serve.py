@@ -41,6 +41,59 @@ def alone(ctx, spec, img):
     return g.fetch()
 
 
+@pytest.mark.parametrize("batched", [True, False], ids=["batched", "plain"])
+def test_native_loop_results_are_the_oracles(ctx, batched):
+    """fast_pump_run serves the same arrivals with the loop in the library:
+    every request is served, no earlier than it arrived, and every result
+    slot holds the oracle's answer for the frame of the last request it
+    served, both on the device and in its pinned host copy."""
+    specs = small_streams()
+    srv = serve.Server(ctx, specs, pool_frames=2, slots_per_stream=3, max_batch=16, inflight=3)
+    print(f"case native loop batched={batched}", flush=True)
+    stats = srv.run_native(0.4, seed=11, batched=batched)
+    assert stats["frames"] == stats["offered_frames"] > 50
+    assert stats["batches"] >= (1 if batched else stats["frames"])
+    assert stats["latency_ms"]["p50"] > 0
+    served, slot_of = stats["served"], stats["slot_of"]
+    assert (slot_of >= 0).all() and (slot_of < 3).all()
+    last = {}
+    for r, (_, s, k) in enumerate(served):
+        last[(s, int(slot_of[r]))] = k
+    assert len(last) >= 8
+    for (s, slot), k in sorted(last.items()):
+        st, spec = srv.streams[s], srv.specs[s]
+        want, _ = oracle.detect_grid(st.host_pool[k % len(st.pool)], spec.width, spec.levels, spec.t, spec.n,
+                                     spec.cell)
+        sl = st.slots[slot]
+        assert np.array_equal(sl.host.numpy().view(fastgrid.FEATURE_DTYPE), want), (s, slot, k)
+        assert np.array_equal(sl.grid.cpu().numpy().view(fastgrid.FEATURE_DTYPE), want), (s, slot, k)
+
+
+def test_native_loop_rejects_bad_arguments(ctx):
+    specs = small_streams()[:1]
+    srv = serve.Server(ctx, specs, pool_frames=1, slots_per_stream=1, max_batch=4, inflight=1)
+    st, spec = srv.streams[0], specs[0]
+    pool = (fastgrid.fast_plane * 1)(*st.pool_planes)
+    upper = (fastgrid.fast_plane * (spec.levels - 1))(*st.slots[0].planes[1:spec.levels])
+    import ctypes
+    out = (ctypes.c_void_p * 1)(st.slots[0].grid.data_ptr())
+    arr = (fastgrid.fast_pump_stream * 1)(fastgrid.fast_pump_stream(
+        spec.levels, spec.t, spec.n, spec.cell, 0, 1, pool, 1, upper, out, None))
+    good = (fastgrid.fast_pump_request * 2)(fastgrid.fast_pump_request(0, 0, 0.0),
+                                             fastgrid.fast_pump_request(0, 1, 0.001))
+    done, slot, nb = fastgrid.fast_pump_run(ctx.handle, arr, 1, good, 2, 1, 4, True, 5.0)
+    assert (done > 0).all() and nb == 2
+    bad_order = (fastgrid.fast_pump_request * 2)(fastgrid.fast_pump_request(0, 0, 0.01),
+                                                  fastgrid.fast_pump_request(0, 1, 0.0))
+    bad_stream = (fastgrid.fast_pump_request * 1)(fastgrid.fast_pump_request(1, 0, 0.0))
+    for args in ((arr, 1, bad_order, 2, 1, 4), (arr, 1, bad_stream, 1, 1, 4), (arr, 1, good, 2, 9, 4),
+                 (arr, 1, good, 2, 0, 4), (arr, 1, good, 2, 1, 0), (arr, 1, good, 0, 1, 4)):
+        with pytest.raises(fastgrid.FastError) as ei:
+            fastgrid.fast_pump_run(ctx.handle, args[0], args[1], args[2], args[3], args[4], args[5], True, 5.0)
+        assert ei.value.code == fastgrid.FAST_EINVAL
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("batched,upload", [(True, False), (False, False), (True, True)],
                          ids=["batched", "plain", "batched_upload"])
 def test_each_result_same_alone_and_in_mix(ctx, batched, upload):
