@@ -398,6 +398,7 @@ def _serve_stats(st: dict) -> dict:
     st.pop("requests")
     st.pop("slot_of", None)
     st.pop("served", None)
+    st.pop("done_s", None)
     for k in ("mpixel_s", "wall_s", "mean_batch"):
         st[k] = round(st[k], 3)
     st["latency_ms"] = {k: (round(v, 4) if v is not None else None) for k, v in st["latency_ms"].items()}
@@ -509,6 +510,13 @@ def serving(ctx, seconds: float, trace_path: str = "") -> dict:
     res["frontend"]["p99_ms_over_runs"] = [r["latency_ms"]["p99"] for r in fe_runs]
     log(f"serving frontend: {fe_runs[0]['frames']} frames, {fe_runs[0]['mpixel_s']} Mpx/s, "
         f"p50 {fe_runs[0]['latency_ms']['p50']} ms p99 {fe_runs[0]['latency_ms']['p99']} ms")
+    # the same with the loop in the library (fast_pump_run_frontend)
+    srv.run_native(0.3, seed=99)
+    fn_runs = [_serve_stats(srv.run_native(seconds * 0.4, seed=41 + rep)) for rep in range(2)]
+    res["frontend_native"] = fn_runs[0]
+    res["frontend_native"]["p99_ms_over_runs"] = [r["latency_ms"]["p99"] for r in fn_runs]
+    log(f"serving frontend_native: {fn_runs[0]['frames']} frames, {fn_runs[0]['mpixel_s']} Mpx/s, "
+        f"p50 {fn_runs[0]['latency_ms']['p50']} ms p99 {fn_runs[0]['latency_ms']['p99']} ms")
     srv.close()
     srv = serve.Server(ctx, specs, pool_frames=4, slots_per_stream=4, max_batch=64, inflight=4,
                        upload=True)

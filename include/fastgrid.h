@@ -424,6 +424,34 @@ int fast_pump_run(fast_ctx *ctx, const fast_pump_stream *streams, int nstreams, 
                   int nreq, int lanes, int max_batch, int batched, double max_seconds, double *done_s,
                   int32_t *slot_of, int32_t *nbatches);
 
+/* The same loop serving the detect-and-track front end (fast_frontend_step)
+ * of every stream: a stream's frames are served in order, one at a time.  A
+ * launch detects (SAD-A) the frames of its streams into their current
+ * pyramids and cell grids (one fast_submit), runs one fast_frontend_step for
+ * them from each stream's previous frame, and copies each step's info to
+ * info_host.  The two pyramids of a stream alternate; level 0 is the pool
+ * frame.  `streams` gives levels, t, n, cell and the pool (slots must be at
+ * least 1; upper, out and host_out are not used); fe[i] holds stream i's
+ * state (device memory unless noted).  A launch holds two of the context's
+ * job tables, so lanes is at most FAST_PUMP_MAX_LANES / 2. */
+typedef struct {
+    const fast_plane *upper;   /* host array of 2 * (levels-1) planes: levels 1.. of pyramid 0, then 1 */
+    fast_feature *grid;        /* this frame's cell winners */
+    float *feats;              /* capacity x 2, live features; in and out across frames */
+    int32_t *count;            /* 1: live features (0 before the stream's first frame) */
+    float *q;                  /* capacity x 4, scratch */
+    int32_t *status;           /* capacity, scratch */
+    int32_t *info;             /* 4: (tracked, re-detected, live, 0) of the last step */
+    void *info_host;           /* pinned host copy of info after each step, or NULL */
+    int32_t capacity;          /* 1..FAST_MAX_TRACKS */
+    int32_t redetect_below;    /* 0..capacity */
+} fast_pump_frontend;
+/* Errors as fast_pump_run, plus those of fast_frontend_step. */
+int fast_pump_run_frontend(fast_ctx *ctx, const fast_pump_stream *streams, const fast_pump_frontend *fe,
+                           int nstreams, const fast_pump_request *reqs, int nreq, int lanes, int max_batch,
+                           int mode, int max_iter, float eps, double max_seconds, double *done_s,
+                           int32_t *nbatches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <mutex>
 #include <string>
@@ -947,18 +948,16 @@ struct PumpSlots {
     size_t out_bytes = 0;
 };
 
-static_assert(sizeof(fast_pump_stream) == 64 && sizeof(fast_pump_request) == 16, "pump ABI layout");
+static_assert(sizeof(fast_pump_stream) == 64 && sizeof(fast_pump_request) == 16 && sizeof(fast_pump_frontend) == 72,
+              "pump ABI layout");
 
 int pump_check(fast_ctx *c, const fast_pump_stream *streams, int nstreams, const fast_pump_request *reqs,
                int nreq) {
     for (int i = 0; i < nstreams; ++i) {
         const fast_pump_stream &S = streams[i];
         if (S.levels < 1 || S.levels > FAST_MAX_LEVELS || S.pool_frames < 1 || !S.pool || S.slots < 1 ||
-            S.slots > 4096 || !S.out || (S.levels > 1 && !S.upper))
+            S.slots > 4096)
             return fail(c, FAST_EINVAL, "pump stream " + std::to_string(i) + " is malformed");
-        for (int k = 0; k < S.slots; ++k)
-            if (!S.out[k] || (S.host_out && !S.host_out[k]))
-                return fail(c, FAST_EINVAL, "pump stream " + std::to_string(i) + " has a NULL slot buffer");
     }
     double last = 0.0;
     for (int r = 0; r < nreq; ++r) {
@@ -974,32 +973,16 @@ int pump_check(fast_ctx *c, const fast_pump_stream *streams, int nstreams, const
 
 }  // namespace
 
-FG_API int fast_pump_run(fast_ctx *c, const fast_pump_stream *streams, int nstreams, const fast_pump_request *reqs,
-                         int nreq, int lanes, int max_batch, int batched, double max_seconds, double *done_s,
-                         int32_t *slot_of, int32_t *nbatches) {
-    if (!c) return FAST_EINVAL;
-    if (!streams || !reqs || !done_s || !slot_of || !nbatches || nstreams < 1 || nreq < 1)
-        return fail(c, FAST_EINVAL, "pump: NULL array, no stream or no request");
-    if (lanes < 1 || lanes > FAST_PUMP_MAX_LANES) return fail(c, FAST_EINVAL, "pump: lanes not in 1..8");
-    if (max_batch < 1 || max_batch > FAST_MAX_JOBS) return fail(c, FAST_EINVAL, "pump: max_batch out of range");
-    if (!(max_seconds > 0.0)) return fail(c, FAST_EINVAL, "pump: max_seconds must be positive");
-    int rc = pump_check(c, streams, nstreams, reqs, nreq);
-    if (rc) return rc;
-    DeviceGuard g(c->device);
-    std::vector<PumpSlots> slots(nstreams);
-    for (int i = 0; i < nstreams; ++i) {
-        const fast_pump_stream &S = streams[i];
-        int gw = 0, gh = 0;
-        if (fast_grid_dims(S.pool[0].width, S.pool[0].height, S.cell, &gw, &gh) != FAST_OK)
-            return fail(c, FAST_EINVAL, "pump stream " + std::to_string(i) + ": bad frame size or cell");
-        slots[i].out_bytes = (size_t)gw * gh * sizeof(fast_feature);
-        slots[i].busy.assign(S.slots, 0);
-        slots[i].planes.resize(S.slots);
-        for (int k = 0; k < S.slots; ++k) {
-            slots[i].planes[k].resize(S.levels);
-            for (int l = 1; l < S.levels; ++l) slots[i].planes[k][l] = S.upper[k * (S.levels - 1) + (l - 1)];
-        }
-    }
+// The loop shared by both entry points.  `slots_of(i)` is stream i's number
+// of result slots; `launch(lane, reqs, n)` enqueues one launch of n requests
+// (their slots already taken, slot_of set) on the lane's stream.
+template <class Launch>
+int pump_loop(fast_ctx *c, int nstreams, const std::vector<int> &nslots, const fast_pump_request *reqs, int nreq,
+              int lanes, int limit, double max_seconds, double *done_s, int32_t *slot_of, int32_t *nbatches,
+              Launch launch) {
+    std::vector<std::vector<char>> busy(nstreams);
+    for (int i = 0; i < nstreams; ++i) busy[i].assign(nslots[i], 0);
+    int rc = FAST_OK;
     std::vector<PumpLane> lane(lanes);
     for (PumpLane &L : lane) {
         hipError_t e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
@@ -1008,11 +991,10 @@ FG_API int fast_pump_run(fast_ctx *c, const fast_pump_stream *streams, int nstre
             rc = hip_fail(c, e, "pump lane setup");
             break;
         }
-        L.reqs.reserve(max_batch);
+        L.reqs.reserve(limit);
     }
     std::vector<std::vector<int>> pending(nstreams);   // per stream, arrived requests in order
     std::vector<size_t> head(nstreams, 0);
-    std::vector<fast_job> jobs(batched ? max_batch : 1);
     for (int r = 0; r < nreq; ++r) {
         done_s[r] = -1.0;
         slot_of[r] = -1;
@@ -1026,8 +1008,7 @@ FG_API int fast_pump_run(fast_ctx *c, const fast_pump_stream *streams, int nstre
         double when = 0.0;
         for (int i = 0; i < nstreams; ++i) {
             if (head[i] >= pending[i].size()) continue;
-            const std::vector<char> &b = slots[i].busy;
-            if (std::find(b.begin(), b.end(), 0) == b.end()) continue;
+            if (std::find(busy[i].begin(), busy[i].end(), 0) == busy[i].end()) continue;
             const double a = reqs[pending[i][head[i]]].arrival_s;
             if (best < 0 || a < when) {
                 best = i;
@@ -1057,7 +1038,7 @@ FG_API int fast_pump_run(fast_ctx *c, const fast_pump_stream *streams, int nstre
             const double tt = now();
             for (int r : L.reqs) {
                 done_s[r] = tt;
-                slots[reqs[r].stream].busy[slot_of[r]] = 0;
+                busy[reqs[r].stream][slot_of[r]] = 0;
             }
             served += (int)L.reqs.size();
             L.reqs.clear();
@@ -1065,39 +1046,17 @@ FG_API int fast_pump_run(fast_ctx *c, const fast_pump_stream *streams, int nstre
         }
         for (PumpLane &L : lane) {   // launches
             if (rc != FAST_OK || L.busy) continue;
-            const int limit = batched ? max_batch : 1;
-            int nj = 0;
             while ((int)L.reqs.size() < limit) {
                 const int i = pick();
                 if (i < 0) break;
                 const int r = pending[i][head[i]++];
-                const fast_pump_stream &S = streams[i];
-                std::vector<char> &b = slots[i].busy;
-                const int k = (int)(std::find(b.begin(), b.end(), 0) - b.begin());
-                b[k] = 1;
+                const int k = (int)(std::find(busy[i].begin(), busy[i].end(), 0) - busy[i].begin());
+                busy[i][k] = 1;
                 slot_of[r] = k;
-                std::vector<fast_plane> &pl = slots[i].planes[k];
-                pl[0] = S.pool[reqs[r].frame % S.pool_frames];
-                jobs[nj] = fast_job{pl.data(), S.levels, S.t, S.n, S.cell, S.out[k], S.score};
-                ++nj;
                 L.reqs.push_back(r);
             }
-            if (nj == 0) break;
-            if (batched) {
-                uint64_t tk = 0;
-                rc = fast_submit(c, jobs.data(), nj, L.stream, &tk);
-            } else {
-                const fast_job &J = jobs[0];
-                rc = fast_detect_grid_score(c, J.pyr, J.levels, J.t, J.n, J.cell, J.score, J.out, L.stream);
-            }
-            for (int q = 0; rc == FAST_OK && q < nj; ++q) {
-                const int r = L.reqs[q];
-                const fast_pump_stream &S = streams[reqs[r].stream];
-                if (!S.host_out) continue;
-                const hipError_t e = hipMemcpyAsync(S.host_out[slot_of[r]], S.out[slot_of[r]],
-                                                    slots[reqs[r].stream].out_bytes, hipMemcpyDeviceToHost, L.stream);
-                if (e != hipSuccess) rc = hip_fail(c, e, "pump result copy");
-            }
+            if (L.reqs.empty()) break;
+            rc = launch(L.stream, L.reqs.data(), (int)L.reqs.size());
             if (rc == FAST_OK) {
                 const hipError_t e = hipEventRecord(L.done, L.stream);
                 if (e != hipSuccess) rc = hip_fail(c, e, "pump event");
@@ -1113,6 +1072,147 @@ FG_API int fast_pump_run(fast_ctx *c, const fast_pump_stream *streams, int nstre
     }
     *nbatches = nb;
     return rc;
+}
+
+int pump_args(fast_ctx *c, const fast_pump_stream *streams, int nstreams, const fast_pump_request *reqs, int nreq,
+              int lanes, int max_batch, double max_seconds, const void *done_s, const void *nbatches) {
+    if (!streams || !reqs || !done_s || !nbatches || nstreams < 1 || nreq < 1)
+        return fail(c, FAST_EINVAL, "pump: NULL array, no stream or no request");
+    if (lanes < 1 || lanes > FAST_PUMP_MAX_LANES) return fail(c, FAST_EINVAL, "pump: lanes not in 1..8");
+    if (max_batch < 1 || max_batch > FAST_MAX_JOBS) return fail(c, FAST_EINVAL, "pump: max_batch out of range");
+    if (!(max_seconds > 0.0)) return fail(c, FAST_EINVAL, "pump: max_seconds must be positive");
+    return pump_check(c, streams, nstreams, reqs, nreq);
+}
+
+FG_API int fast_pump_run(fast_ctx *c, const fast_pump_stream *streams, int nstreams, const fast_pump_request *reqs,
+                         int nreq, int lanes, int max_batch, int batched, double max_seconds, double *done_s,
+                         int32_t *slot_of, int32_t *nbatches) {
+    if (!c) return FAST_EINVAL;
+    if (!slot_of) return fail(c, FAST_EINVAL, "pump: slot_of is NULL");
+    int rc = pump_args(c, streams, nstreams, reqs, nreq, lanes, max_batch, max_seconds, done_s, nbatches);
+    if (rc) return rc;
+    for (int i = 0; i < nstreams; ++i) {
+        const fast_pump_stream &S = streams[i];
+        if (!S.out || (S.levels > 1 && !S.upper))
+            return fail(c, FAST_EINVAL, "pump stream " + std::to_string(i) + " has no result slots");
+        for (int k = 0; k < S.slots; ++k)
+            if (!S.out[k] || (S.host_out && !S.host_out[k]))
+                return fail(c, FAST_EINVAL, "pump stream " + std::to_string(i) + " has a NULL slot buffer");
+    }
+    DeviceGuard g(c->device);
+    std::vector<int> nslots(nstreams);
+    std::vector<size_t> out_bytes(nstreams);
+    std::vector<std::vector<std::vector<fast_plane>>> planes(nstreams);   // per stream, slot: levels planes
+    for (int i = 0; i < nstreams; ++i) {
+        const fast_pump_stream &S = streams[i];
+        int gw = 0, gh = 0;
+        if (fast_grid_dims(S.pool[0].width, S.pool[0].height, S.cell, &gw, &gh) != FAST_OK)
+            return fail(c, FAST_EINVAL, "pump stream " + std::to_string(i) + ": bad frame size or cell");
+        out_bytes[i] = (size_t)gw * gh * sizeof(fast_feature);
+        nslots[i] = S.slots;
+        planes[i].resize(S.slots);
+        for (int k = 0; k < S.slots; ++k) {
+            planes[i][k].resize(S.levels);
+            for (int l = 1; l < S.levels; ++l) planes[i][k][l] = S.upper[k * (S.levels - 1) + (l - 1)];
+        }
+    }
+    std::vector<fast_job> jobs(batched ? max_batch : 1);
+    auto launch = [&](hipStream_t s, const int *rq, int n) {
+        for (int q = 0; q < n; ++q) {
+            const fast_pump_request &R = reqs[rq[q]];
+            const fast_pump_stream &S = streams[R.stream];
+            std::vector<fast_plane> &pl = planes[R.stream][slot_of[rq[q]]];
+            pl[0] = S.pool[R.frame % S.pool_frames];
+            jobs[q] = fast_job{pl.data(), S.levels, S.t, S.n, S.cell, S.out[slot_of[rq[q]]], S.score};
+        }
+        int rc2;
+        if (batched) {
+            uint64_t tk = 0;
+            rc2 = fast_submit(c, jobs.data(), n, s, &tk);
+        } else {
+            const fast_job &J = jobs[0];
+            rc2 = fast_detect_grid_score(c, J.pyr, J.levels, J.t, J.n, J.cell, J.score, J.out, s);
+        }
+        for (int q = 0; rc2 == FAST_OK && q < n; ++q) {
+            const fast_pump_request &R = reqs[rq[q]];
+            const fast_pump_stream &S = streams[R.stream];
+            if (!S.host_out) continue;
+            const hipError_t e = hipMemcpyAsync(S.host_out[slot_of[rq[q]]], S.out[slot_of[rq[q]]], out_bytes[R.stream],
+                                                hipMemcpyDeviceToHost, s);
+            if (e != hipSuccess) rc2 = hip_fail(c, e, "pump result copy");
+        }
+        return rc2;
+    };
+    return pump_loop(c, nstreams, nslots, reqs, nreq, lanes, batched ? max_batch : 1, max_seconds, done_s, slot_of,
+                     nbatches, launch);
+}
+
+FG_API int fast_pump_run_frontend(fast_ctx *c, const fast_pump_stream *streams, const fast_pump_frontend *fe,
+                                  int nstreams, const fast_pump_request *reqs, int nreq, int lanes, int max_batch,
+                                  int mode, int max_iter, float eps, double max_seconds, double *done_s,
+                                  int32_t *nbatches) {
+    if (!c) return FAST_EINVAL;
+    if (!fe) return fail(c, FAST_EINVAL, "pump: fe is NULL");
+    int rc = pump_args(c, streams, nstreams, reqs, nreq, lanes, max_batch, max_seconds, done_s, nbatches);
+    if (rc) return rc;
+    rc = check_track_params(c, mode, max_iter, eps);
+    if (rc) return rc;
+    if (lanes > FAST_PUMP_MAX_LANES / 2) return fail(c, FAST_EINVAL, "pump: at most 4 front-end lanes");
+    for (int i = 0; i < nstreams; ++i) {
+        const fast_pump_frontend &F = fe[i];
+        if (!F.grid || !F.feats || !F.count || !F.q || !F.status || !F.info || (streams[i].levels > 1 && !F.upper) ||
+            F.capacity < 1 || F.capacity > FAST_MAX_TRACKS || F.redetect_below < 0 ||
+            F.redetect_below > F.capacity)
+            return fail(c, FAST_EINVAL, "pump front end " + std::to_string(i) + " is malformed");
+    }
+    DeviceGuard g(c->device);
+    // per stream: the two alternating pyramids (level 0 set per frame), which
+    // one is current, and whether a previous frame exists
+    std::vector<std::array<std::vector<fast_plane>, 2>> pyr(nstreams);
+    std::vector<int> cur(nstreams, 0), frames(nstreams, 0), nslots(nstreams, 1);
+    for (int i = 0; i < nstreams; ++i) {
+        const int L = streams[i].levels;
+        for (int b = 0; b < 2; ++b) {
+            pyr[i][b].resize(L);
+            for (int l = 1; l < L; ++l) pyr[i][b][l] = fe[i].upper[b * (L - 1) + (l - 1)];
+        }
+    }
+    std::vector<int32_t> slot_of(nreq);
+    std::vector<fast_job> jobs(max_batch);
+    std::vector<fast_frontend_job> fjobs(max_batch);
+    auto launch = [&](hipStream_t s, const int *rq, int n) {
+        for (int q = 0; q < n; ++q) {
+            const fast_pump_request &R = reqs[rq[q]];
+            const fast_pump_stream &S = streams[R.stream];
+            std::vector<fast_plane> &pc = pyr[R.stream][cur[R.stream]];
+            pc[0] = S.pool[R.frame % S.pool_frames];
+            jobs[q] = fast_job{pc.data(), S.levels, S.t, S.n, S.cell, fe[R.stream].grid, FAST_SCORE_SADA};
+        }
+        uint64_t tk = 0;
+        int rc2 = fast_submit(c, jobs.data(), n, s, &tk);
+        if (rc2 != FAST_OK) return rc2;
+        for (int q = 0; q < n; ++q) {
+            const int i = reqs[rq[q]].stream;
+            const fast_pump_frontend &F = fe[i];
+            fjobs[q] = fast_frontend_job{frames[i] > 0 ? pyr[i][1 - cur[i]].data() : nullptr, pyr[i][cur[i]].data(),
+                                         streams[i].levels, F.grid, streams[i].cell, F.capacity, F.redetect_below,
+                                         F.feats, F.count, F.q, F.status, F.info};
+        }
+        rc2 = fast_frontend_step(c, fjobs.data(), n, mode, max_iter, eps, s, &tk);
+        for (int q = 0; rc2 == FAST_OK && q < n; ++q) {
+            const int i = reqs[rq[q]].stream;
+            if (fe[i].info_host) {
+                const hipError_t e = hipMemcpyAsync(fe[i].info_host, fe[i].info, 4 * sizeof(int32_t),
+                                                    hipMemcpyDeviceToHost, s);
+                if (e != hipSuccess) rc2 = hip_fail(c, e, "pump info copy");
+            }
+            cur[i] = 1 - cur[i];
+            ++frames[i];
+        }
+        return rc2;
+    };
+    return pump_loop(c, nstreams, nslots, reqs, nreq, lanes, max_batch, max_seconds, done_s, slot_of.data(), nbatches,
+                     launch);
 }
 
 FG_API int fast_poll(fast_ctx *c, uint64_t ticket) {

@@ -34,7 +34,7 @@ EXPORTS = ("fast_ctx_create", "fast_ctx_destroy", "fast_strerror", "fast_last_er
            "fast_detect_grid_score", "fast_score_maps", "fast_nms_grid",
            "fast_submit", "fast_submit_static", "fast_poll", "fast_wait", "fast_plan_create", "fast_plan_launch",
            "fast_plan_destroy", "fast_set_launch", "fast_track", "fast_set_shape_table",
-           "fast_shape_region_of", "fast_frontend_step", "fast_pump_run")
+           "fast_shape_region_of", "fast_frontend_step", "fast_pump_run", "fast_pump_run_frontend")
 
 
 class fast_plane(ctypes.Structure):
@@ -76,6 +76,13 @@ class fast_pump_stream(ctypes.Structure):
 
 class fast_pump_request(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_int32), ("frame", ctypes.c_int32), ("arrival_s", ctypes.c_double)]
+
+
+class fast_pump_frontend(ctypes.Structure):
+    _fields_ = [("upper", ctypes.POINTER(fast_plane)), ("grid", ctypes.c_void_p), ("feats", ctypes.c_void_p),
+                ("count", ctypes.c_void_p), ("q", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("info", ctypes.c_void_p), ("info_host", ctypes.c_void_p), ("capacity", ctypes.c_int32),
+                ("redetect_below", ctypes.c_int32)]
 
 
 FAST_PUMP_MAX_LANES = 8
@@ -132,6 +139,10 @@ def load() -> ctypes.CDLL:
             "fast_pump_run": ([vp, ctypes.POINTER(fast_pump_stream), i32, ctypes.POINTER(fast_pump_request), i32,
                                i32, i32, i32, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], i32),
+            "fast_pump_run_frontend": ([vp, ctypes.POINTER(fast_pump_stream), ctypes.POINTER(fast_pump_frontend),
+                                        i32, ctypes.POINTER(fast_pump_request), i32, i32, i32, i32, i32,
+                                        ctypes.c_float, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int32)], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -285,6 +296,18 @@ def fast_pump_run(ctx, streams, nstreams: int, reqs, nreq: int, lanes: int, max_
                                      slot.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(nb)),
            "fast_pump_run")
     return done, slot, nb.value
+
+
+def fast_pump_run_frontend(ctx, streams, fe, nstreams: int, reqs, nreq: int, lanes: int, max_batch: int,
+                           mode: int, max_iter: int, eps: float, max_seconds: float):
+    """Serve nreq front-end requests natively; returns (done_s, nbatches)."""
+    done = np.zeros(nreq, dtype=np.float64)
+    nb = ctypes.c_int32()
+    _check(ctx, load().fast_pump_run_frontend(ctx, streams, fe, nstreams, reqs, nreq, lanes, max_batch, mode,
+                                              max_iter, eps, max_seconds,
+                                              done.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              ctypes.byref(nb)), "fast_pump_run_frontend")
+    return done, nb.value
 
 
 def _stream(stream):

@@ -500,27 +500,46 @@ class Server:
         in the library (fast_pump_run): it replays the arrival schedule by the
         host clock, launches, copies results and polls completions without
         returning to Python.  Serves the streams resident now (no joins or
-        leaves, no uploads, no front end); frames of other streams are
-        refused.  Returns the same statistics as run(), plus "slot_of" (the
-        result slot each request used), in request order."""
-        if self.upload or self.frontend is not None:
-            raise ValueError("the native loop serves resident frames by detection only")
+        leaves, no uploads); frames of other streams are
+        refused.  With a front end (fast_pump_run_frontend) every stream
+        starts afresh: its first frame in the run has no previous frame.
+        Returns the same statistics as run(), plus "slot_of" (the result slot
+        each request used), "served" (time, stream, frame of each request)
+        and "done_s" (when its completion was seen), in request order."""
+        if self.upload:
+            raise ValueError("the native loop serves resident frames")
         torch = self.torch
         live = [i for i, st in enumerate(self.streams) if st is not None]
         index = {i: j for j, i in enumerate(live)}
         arr = (fastgrid.fast_pump_stream * len(live))()
+        fes = (fastgrid.fast_pump_frontend * len(live))()
         keep = []   # ctypes arrays the descriptors point into
         for j, i in enumerate(live):
             st, spec = self.streams[i], self.specs[i]
             nup = spec.levels - 1
             pool = (fastgrid.fast_plane * len(st.pool_planes))(*st.pool_planes)
+            keep.append(pool)
+            if self.frontend is not None:
+                fe = st.fe
+                upper = (fastgrid.fast_plane * max(1, 2 * nup))()
+                for b in range(2):
+                    for lv in range(nup):
+                        upper[b * nup + lv] = fe.planes[b][lv + 1]
+                keep.append(upper)
+                fes[j] = fastgrid.fast_pump_frontend(
+                    upper, fe.grid.data_ptr(), fe.feats.data_ptr(), fe.count.data_ptr(), fe.q.data_ptr(),
+                    fe.status.data_ptr(), fe.info.data_ptr(), fe.info_host.data_ptr(), self.frontend.target,
+                    fe.below)
+                arr[j] = fastgrid.fast_pump_stream(spec.levels, spec.t, spec.n, spec.cell, 0, len(pool), pool, 1,
+                                                   None, None, None)
+                continue
             upper = (fastgrid.fast_plane * max(1, len(st.slots) * nup))()
             for k, sl in enumerate(st.slots):
                 for lv in range(nup):
                     upper[k * nup + lv] = sl.planes[lv + 1]
             out = (ctypes.c_void_p * len(st.slots))(*[sl.grid.data_ptr() for sl in st.slots])
             host = (ctypes.c_void_p * len(st.slots))(*[sl.host.data_ptr() for sl in st.slots])
-            keep += [pool, upper, out, host]
+            keep += [upper, out, host]
             arr[j] = fastgrid.fast_pump_stream(
                 spec.levels, spec.t, spec.n, spec.cell, 0, len(pool), pool, len(st.slots), upper, out,
                 host if self.download else None)
@@ -533,13 +552,35 @@ class Server:
         torch.cuda.synchronize()
         gc_was = gc.isenabled()
         gc.disable()
+        limit = max_seconds if max_seconds is not None else 3.0 * duration_s + 10.0
         try:
-            done, slot_of, nb = fastgrid.fast_pump_run(
-                self.ctx.handle, arr, len(live), reqs, len(served), self.inflight, self.max_batch, batched,
-                max_seconds if max_seconds is not None else 3.0 * duration_s + 10.0)
+            if self.frontend is not None:
+                fp = self.frontend
+                done, nb = fastgrid.fast_pump_run_frontend(
+                    self.ctx.handle, arr, fes, len(live), reqs, len(served), self.inflight, self.max_batch,
+                    fp.mode, fp.max_iter, fp.eps, limit)
+                slot_of = np.zeros(len(served), dtype=np.int32)
+            else:
+                done, slot_of, nb = fastgrid.fast_pump_run(
+                    self.ctx.handle, arr, len(live), reqs, len(served), self.inflight, self.max_batch, batched,
+                    limit)
         finally:
             if gc_was:
                 gc.enable()
+        if self.frontend is not None:
+            # the native loop starts every stream afresh (its first frame has
+            # no previous one) with pyramid 0 current; carry its end state over
+            # so that a later run() continues each stream's sequence
+            last = {}
+            counts = collections.Counter()
+            for _, s_, k in served:
+                last[s_] = k
+                counts[s_] += 1
+            for s_, n_ in counts.items():
+                fe, st = self.streams[s_].fe, self.streams[s_]
+                fe.planes[(n_ - 1) % 2][0] = st.pool_planes[last[s_] % len(st.pool)]
+                fe.cur = n_ % 2
+                fe.frames = n_
         lat_ms = [(d - t) * 1e3 for d, (t, _, _) in zip(done, served)]
         per_res = collections.defaultdict(list)
         for (t, s, _), l in zip(served, lat_ms):
@@ -547,7 +588,8 @@ class Server:
         wall = float(done.max()) if len(done) else 0.0
         px = sum(self.specs[s].width * self.specs[s].height for _, s, _ in served)
         return {
-            "mode": ("batched" if batched else "plain") + "-native", "rate_scale": rate_scale,
+            "mode": ("frontend" if self.frontend is not None else ("batched" if batched else "plain")) + "-native",
+            "rate_scale": rate_scale,
             "frames": len(served), "offered_frames": len(schedule), "refused_frames": sum(refused.values()),
             "refused_by_stream": dict(refused), "duration_s": duration_s,
             "wall_s": wall, "mpixel_s": px / wall / 1e6 if wall > 0 else 0.0,
@@ -556,7 +598,7 @@ class Server:
             "batches": nb, "mean_batch": len(served) / nb if nb else 0.0,
             "streams_admitted": len(live), "streams_waiting": len(self.waiting),
             "streams_rejected": len(self.waiting), "resident_bytes": self.used, "hbm_budget": self.hbm_budget,
-            "requests": [], "slot_of": slot_of, "served": served,
+            "requests": [], "slot_of": slot_of, "served": served, "done_s": done,
         }
 
     def _frontend_batch(self, group, lane, hs) -> int:

@@ -43,6 +43,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(fastgrid.fast_shape_region) == 20
     assert ctypes.sizeof(fastgrid.fast_pump_stream) == 64
     assert ctypes.sizeof(fastgrid.fast_pump_request) == 16
+    assert ctypes.sizeof(fastgrid.fast_pump_frontend) == 72
 
 
 def test_pyr_and_grid_dims():

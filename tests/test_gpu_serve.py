@@ -226,3 +226,34 @@ def test_frontend_serving_matches_oracle_loop(ctx):
             prev, feats_in = want[4], feats
     assert tracked > 0
     srv.close()
+
+
+def test_native_frontend_loop_equals_the_python_loop(ctx):
+    """fast_pump_run_frontend serves the same arrivals as the Python loop
+    (whose steps the test above checks against the oracle).  A stream's
+    computation does not depend on which streams share its launches, so every
+    stream ends with the same feature list and step summary, bit for bit, and
+    its frames are served in order."""
+    specs = [TexturedStream(0, 320, 240, 3, 10, 9, 16, 150.0, 91),
+             TexturedStream(1, 640, 480, 4, 8, 10, 32, 200.0, 92),
+             TexturedStream(2, 376, 240, 3, 15, 12, 16, 250.0, 93)]
+    fp = serve.FrontendParams(target=60, redetect_frac=0.5, mode=3, max_iter=30, eps=1e-3)
+    print("case serve frontend native", flush=True)
+    py = serve.Server(ctx, specs, pool_frames=3, max_batch=16, inflight=3, frontend=fp)
+    a = py.run(0.1, seed=5)
+    nat = serve.Server(ctx, specs, pool_frames=3, max_batch=16, inflight=3, frontend=fp)
+    b = nat.run_native(0.1, seed=5)
+    torch.cuda.synchronize()
+    assert b["mode"] == "frontend-native" and b["frames"] == a["frames"] > 20
+    for s in range(len(specs)):
+        fa, fb = py.streams[s].fe, nat.streams[s].fe
+        na, nb = int(fa.count.cpu()[0]), int(fb.count.cpu()[0])
+        assert na == nb, s
+        assert np.array_equal(fa.info.cpu().numpy(), fb.info.cpu().numpy()), s
+        assert np.array_equal(fa.info_host.numpy(), fb.info_host.numpy()), s
+        assert torch.equal(fa.feats[:na].cpu(), fb.feats[:nb].cpu()), s
+        done = [d for d, (_, st, _) in zip(b["done_s"], b["served"]) if st == s]
+        assert done == sorted(done), s   # a stream's frames complete in arrival order
+    assert b["frames"] == sum(fb.frames for fb in (nat.streams[s].fe for s in range(len(specs))))
+    py.close()
+    nat.close()
