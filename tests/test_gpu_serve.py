@@ -91,6 +91,11 @@ def test_native_loop_rejects_bad_arguments(ctx):
         with pytest.raises(fastgrid.FastError) as ei:
             fastgrid.fast_pump_run(ctx.handle, args[0], args[1], args[2], args[3], args[4], args[5], True, 5.0)
         assert ei.value.code == fastgrid.FAST_EINVAL
+    # arrivals later than the run's time limit: the loop gives up, launching nothing
+    late = (fastgrid.fast_pump_request * 1)(fastgrid.fast_pump_request(0, 0, 5.0))
+    with pytest.raises(fastgrid.FastError) as ei:
+        fastgrid.fast_pump_run(ctx.handle, arr, 1, late, 1, 1, 4, True, 0.02)
+    assert ei.value.code == fastgrid.FAST_ETIMEDOUT
     torch.cuda.synchronize()
 
 
