@@ -860,11 +860,16 @@ __device__ void load_tile(uint8_t *tile, const uint8_t *img, int H, int P, int t
 }
 
 // Four pyramid pixels from two rows of eight: (a+b+c+d+2)>>2 per 2x2 block.
+// Bytes 0, 2 and bytes 1, 3 of each word go to 16-bit lanes with one v_perm
+// each; a block's sum is at most 4 * 255 + 2, so no lane carries into the
+// next.  After the shift by 2 each lane's result is its low byte (the bits
+// shifted in from the lane above land in the byte the final v_perm skips).
 __device__ __forceinline__ uint32_t halve4(uint2 a, uint2 b) {
-    const uint32_t m = 0x00FF00FFu;
-    const uint32_t s0 = (a.x & m) + ((a.x >> 8) & m) + (b.x & m) + ((b.x >> 8) & m) + 0x00020002u;
-    const uint32_t s1 = (a.y & m) + ((a.y >> 8) & m) + (b.y & m) + ((b.y >> 8) & m) + 0x00020002u;
-    return __builtin_amdgcn_perm((s1 >> 2) & m, (s0 >> 2) & m, 0x06040200u);
+    auto even = [](uint32_t x) { return __builtin_amdgcn_perm(0u, x, 0x0c020c00u); };
+    auto odd = [](uint32_t x) { return __builtin_amdgcn_perm(0u, x, 0x0c030c01u); };
+    const uint32_t s0 = even(a.x) + odd(a.x) + even(b.x) + odd(b.x) + 0x00020002u;
+    const uint32_t s1 = even(a.y) + odd(a.y) + even(b.y) + odd(b.y) + 0x00020002u;
+    return __builtin_amdgcn_perm(s1 >> 2, s0 >> 2, 0x06040200u);
 }
 
 // Levels 1 and 2 of a fused tile in one pass (tw a multiple of 16): a task
@@ -1154,17 +1159,26 @@ __device__ void detect_region_upper(const fg_job &J, int region, uint8_t *smem) 
 // column i % 8 of level-0 tile rows 4(i/8) .. 4(i/8)+3 (workgroups of at
 // least 256 threads cover a fused tile), so it holds whole 16 x 4 blocks and
 // builds the 8 x 2 level-1 and 4 x 1 level-2 pixels they cover in registers.
+//
+// The loads go through a buffer resource over the plane rows the tile covers
+// (H * P bytes of a plane are addressable): a row above or below the plane
+// reads zero through the buffer's range check, and a chunk left or right of
+// the plane reads bytes of a neighbouring row.  No pixel outside the plane is
+// ever used as a pixel value (it is never testable, never inside a testable
+// pixel's circle, and never written to a level plane), so the loads need no
+// other guard.  Chunks a thread does not load keep stale values, which
+// quad_commit never reads.
 __device__ __forceinline__ void quad_issue(TileRegs &R, const uint8_t *img, int H, int P, const Stage &st) {
     const int ch = threadIdx.x & 7, q = threadIdx.x >> 3;
-    const int gx = st.tx + 16 * ch;
-    const bool ok = ch < (st.tw >> 4) && 4 * q < st.th && gx >= 0 && gx < P;
-    const uint8_t *row = img + (ptrdiff_t)(st.ty + 4 * q) * P + gx;
+    if (ch >= (st.tw >> 4) || 4 * q >= st.th) return;
+    const int y0 = max(st.ty, 0), y1 = min(st.ty + st.th, H);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(img + (ptrdiff_t)y0 * P), (short)0, max(y1 - y0, 0) * P, 0x00020000);
+    int off = (st.ty + 4 * q - y0) * P + st.tx + 16 * ch;   // negative: out of range, reads zero
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int gy = st.ty + 4 * q + j;
-        R.v[j] = u32x4{0u, 0u, 0u, 0u};
-        if (ok && 4 * q + j < st.th && gy >= 0 && gy < H) R.v[j] = gload<u32x4>(row);
-        row += P;
+        R.v[j] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+        off += P;
     }
 }
 
