@@ -771,24 +771,25 @@ __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Ge
         __builtin_amdgcn_s_setprio(0);
         return;
     }
-    // P5: 3x3 NMS of the sub-tile's own pixels, then the cell keys
+    // P5: 3x3 NMS of the sub-tile's own pixels, then the cell keys.  A lane
+    // issues its nine score reads together, so the test costs one LDS round
+    // trip; a ring pixel (its own sub-tile suppresses it) reads around a
+    // fixed entry of the level-0 map instead and is masked off.
     for (int i = lane; i < n2; i += 64) {
         const uint16_t e = list[i];
         const int l = e >> 14;
         int row, col;
         tile_rc(e & 0x3FFF, row, col);
-        if (row < sel3(l, m0.rlo, m1.rlo, m2.rlo) || row >= sel3(l, m0.rhi, m1.rhi, m2.rhi) ||
-            col < sel3(l, m0.clo, m1.clo, m2.clo) || col >= sel3(l, m0.chi, m1.chi, m2.chi))
-            continue;   // ring pixel: its own sub-tile suppresses it
+        const bool own = (row >= sel3(l, m0.rlo, m1.rlo, m2.rlo)) & (row < sel3(l, m0.rhi, m1.rhi, m2.rhi)) &
+                         (col >= sel3(l, m0.clo, m1.clo, m2.clo)) & (col < sel3(l, m0.chi, m1.chi, m2.chi));
         constexpr int mp = MP;
-        const uint16_t *q = maps + row * mp + col + sel3(l, m0.mbias, m1.mbias, m2.mbias);
+        const uint16_t *q = maps + (own ? row * mp + col + sel3(l, m0.mbias, m1.mbias, m2.mbias) : OFF_M0 / 2 + mp + 1);
         const uint32_t s = q[0];
-        if (s == 0) continue;
         // earlier neighbours in row-major order must be strictly lower,
         // later ones lower or equal
-        const bool keep = s > q[-mp - 1] && s > q[-mp] && s > q[-mp + 1] && s > q[-1] &&
-                          s >= q[1] && s >= q[mp - 1] && s >= q[mp] && s >= q[mp + 1];
-        if (!keep) continue;
+        const uint32_t earlier = max(max((uint32_t)q[-mp - 1], (uint32_t)q[-mp]), max((uint32_t)q[-mp + 1], (uint32_t)q[-1]));
+        const uint32_t later = max(max((uint32_t)q[1], (uint32_t)q[mp - 1]), max((uint32_t)q[mp], (uint32_t)q[mp + 1]));
+        if (!(own & (s != 0) & (s > earlier) & (s >= later))) continue;
         const int cw = sel3(l, m0.cw, m1.cw, m2.cw);
         const int ox = col + sel3(l, m0.xo, m1.xo, m2.xo);
         const int oy = row + sel3(l, m0.yo, m1.yo, m2.yo);
@@ -1200,17 +1201,17 @@ __device__ __forceinline__ void store_piece(uint8_t *plane, int P, int y, int x,
 }
 
 // Commit a quad-staged level-0 tile to LDS, build levels 1 and 2 of it into
-// LDS from registers (rows past the tile are zero and only feed level rows
-// past the level tile, which nothing reads), and write the sub-tile's own
-// level-1 and level-2 pixels to their planes.
+// LDS from registers, and write the sub-tile's own level-1 and level-2 pixels
+// to their planes.  A quad's rows past the tile (at most three, still inside
+// the 96 level-0 rows of the LDS tile) are committed too: nothing reads them,
+// and the level rows they feed lie past the level tiles.
 __device__ void quad_commit(uint8_t *smem, const TileRegs &R, const Stage &st, const fg_job &J, const Geo &g1,
                             const Geo &g2) {
     const int ch = threadIdx.x & 7, q = threadIdx.x >> 3;
     if (ch >= (st.tw >> 4) || 4 * q >= st.th) return;
     uint8_t *t0 = smem + T0 + 4 * q * LP + 16 * ch;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-        if (4 * q + j < st.th) *(u32x4 *)(t0 + j * LP) = R.v[j];
+    for (int j = 0; j < 4; ++j) *(u32x4 *)(t0 + j * LP) = R.v[j];
     const int nl = fused_levels(J);
     if (nl < 2) return;
     const u32x4 a = R.v[0], b = R.v[1], c = R.v[2], d = R.v[3];
