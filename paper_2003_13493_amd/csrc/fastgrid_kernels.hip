@@ -133,6 +133,18 @@ __device__ __forceinline__ int div_small(int a, int b) {
     return (int)(((float)a + 0.5f) * __builtin_amdgcn_rcpf((float)b));
 }
 
+// An LDS pointer the compiler cannot see through.  Reads at constant
+// non-negative offsets from it then share one address register and carry the
+// offsets in the instructions' (unsigned) immediate fields, instead of the
+// compiler folding the base into each address and adding negative offsets
+// with separate instructions.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(3))) T *lds_base(const T *p) {
+    const __attribute__((address_space(3))) T *q = (const __attribute__((address_space(3))) T *)p;
+    asm("" : "+v"(q));
+    return q;
+}
+
 __device__ __forceinline__ int lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
@@ -285,7 +297,7 @@ template <int KIND>
 __device__ __forceinline__ uint32_t full_score(const uint8_t *p, int t, int n) {
     // every read is at a non-negative constant offset from the circle's
     // top-left corner, so all 17 share one address register
-    const uint8_t *q = p - CORNER;
+    const auto q = lds_base(p - CORNER);
     const uint32_t cv = q[CORNER];
     const uint32_t hi = cv + (uint32_t)t;
     const uint32_t lo = (int)cv - t > 0 ? cv - (uint32_t)t : 0u;   // darker needs v < c-t; none if c-t <= 0
@@ -439,25 +451,29 @@ struct Px8 {
 
 template <bool A8>
 __device__ __forceinline__ Px8 load8(const uint8_t *smem, uint32_t off) {
-    const uint8_t *p = smem + off;
+    // every read at a non-negative offset from the word 4 bytes before the
+    // group's pixel three rows up
+    const auto b = lds_base((const uint32_t *)(smem + off - 3 * LP - 4));
+    constexpr int R3 = 3 * LP / 4;   // three rows, in words
     Px8 x;
     if constexpr (A8) {
-        const u32x2 lo = *(const u32x2 *)__builtin_assume_aligned(p - 4, 8);
-        const u32x2 hi = *(const u32x2 *)__builtin_assume_aligned(p + 4, 8);
+        // b is 8-aligned here (LP and the group's offset - 4 are)
+        const auto b2 = (const __attribute__((address_space(3))) u32x2 *)b;
+        const u32x2 lo = b2[R3 / 2], hi = b2[R3 / 2 + 1];
         x.D0 = lo.x;
         x.D1 = lo.y;
         x.D2 = hi.x;
         x.D3 = hi.y;
     } else {
-        x.D0 = *(const uint32_t *)(p - 4);
-        x.D1 = *(const uint32_t *)(p);
-        x.D2 = *(const uint32_t *)(p + 4);
-        x.D3 = *(const uint32_t *)(p + 8);
+        x.D0 = b[R3];
+        x.D1 = b[R3 + 1];
+        x.D2 = b[R3 + 2];
+        x.D3 = b[R3 + 3];
     }
-    x.N0 = *(const uint32_t *)(p - 3 * LP);
-    x.N1 = *(const uint32_t *)(p - 3 * LP + 4);
-    x.S0 = *(const uint32_t *)(p + 3 * LP);
-    x.S1 = *(const uint32_t *)(p + 3 * LP + 4);
+    x.N0 = b[1];
+    x.N1 = b[2];
+    x.S0 = b[2 * R3 + 1];
+    x.S1 = b[2 * R3 + 2];
     return x;
 }
 
@@ -607,7 +623,7 @@ __device__ int pass_even8(const uint8_t *smem, int t, int k8, uint16_t *list, in
         const int i = i0 + lane;
         const uint16_t e = list[i];
         const bool valid = i < n1 && e != NO_ENTRY;
-        const uint8_t *q = smem + (valid ? (e & 0x3FFFu) : SAFE_OFF) - CORNER;
+        const auto q = lds_base(smem + (valid ? (e & 0x3FFFu) : SAFE_OFF) - CORNER);
         const int cv = q[CORNER];
         const int hi = cv + t, lo = cv - t;
         uint32_t bm = 0, dm = 0;
@@ -783,12 +799,15 @@ __device__ void run_passes(uint8_t *smem, const Geo &g0, const Geo &g1, const Ge
         const bool own = (row >= sel3(l, m0.rlo, m1.rlo, m2.rlo)) & (row < sel3(l, m0.rhi, m1.rhi, m2.rhi)) &
                          (col >= sel3(l, m0.clo, m1.clo, m2.clo)) & (col < sel3(l, m0.chi, m1.chi, m2.chi));
         constexpr int mp = MP;
-        const uint16_t *q = maps + (own ? row * mp + col + sel3(l, m0.mbias, m1.mbias, m2.mbias) : OFF_M0 / 2 + mp + 1);
-        const uint32_t s = q[0];
+        // q: the upper-left neighbour
+        const auto q = lds_base(maps + (own ? row * mp + col + sel3(l, m0.mbias, m1.mbias, m2.mbias) : OFF_M0 / 2 + mp + 1) -
+                                mp - 1);
+        const uint32_t s = q[mp + 1];
         // earlier neighbours in row-major order must be strictly lower,
         // later ones lower or equal
-        const uint32_t earlier = max(max((uint32_t)q[-mp - 1], (uint32_t)q[-mp]), max((uint32_t)q[-mp + 1], (uint32_t)q[-1]));
-        const uint32_t later = max(max((uint32_t)q[1], (uint32_t)q[mp - 1]), max((uint32_t)q[mp], (uint32_t)q[mp + 1]));
+        const uint32_t earlier = max(max((uint32_t)q[0], (uint32_t)q[1]), max((uint32_t)q[2], (uint32_t)q[mp]));
+        const uint32_t later =
+            max(max((uint32_t)q[mp + 2], (uint32_t)q[2 * mp]), max((uint32_t)q[2 * mp + 1], (uint32_t)q[2 * mp + 2]));
         if (!(own & (s != 0) & (s > earlier) & (s >= later))) continue;
         const int cw = sel3(l, m0.cw, m1.cw, m2.cw);
         const int ox = col + sel3(l, m0.xo, m1.xo, m2.xo);
