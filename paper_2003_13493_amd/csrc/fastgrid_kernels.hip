@@ -1108,8 +1108,9 @@ __device__ __forceinline__ void keys_clear(uint32_t *keys, int n) {
 }
 
 // Decode the region's cell keys into output slots.
-__device__ void keys_write(const fg_job &J, const Region &R, const uint32_t *keys) {
-    for (int i = threadIdx.x; i < R.ncx * R.ncy; i += blockDim.x) {
+__device__ void keys_write(const fg_job &J, const Region &R, const uint32_t *keys, int tid = threadIdx.x,
+                           int nthreads = blockDim.x) {
+    for (int i = tid; i < R.ncx * R.ncy; i += nthreads) {
         const int qy = div_small(i, R.ncx);   // i < MAX_KEYS
         const int cx = R.rxi * J.rcells + i - qy * R.ncx, cy = R.ryi * J.rcells + qy;
         const uint32_t key = keys[i];
@@ -1174,6 +1175,10 @@ __device__ void detect_region_upper(const fg_job &J, int region, uint8_t *smem) 
     __syncthreads();
     keys_write(J, R, keys);
 }
+
+// Threads that own a quad of a fused level-0 tile (at most 96 rows of 4).
+constexpr int QUAD_THREADS = 8 * (96 / 4);
+static_assert(SUB + 2 * (4 << (MAX_FUSED - 1)) <= 96, "fused tiles have at most 96 level-0 rows");
 
 // Tile staging of the pipelined kernel: thread i owns the 16-byte chunk
 // column i % 8 of level-0 tile rows 4(i/8) .. 4(i/8)+3 (workgroups of at
@@ -1500,10 +1505,6 @@ detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__
         const Stage st = fused_stage(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1);
         uint32_t *keys = (uint32_t *)(smem + (b ? OFF_KEYS2 : OFF_KEYS));
         __syncthreads();   // [A]
-        if (have_prev) {
-            const fg_job &Jp = jobs[prev.job];
-            keys_write(Jp, region_of(Jp, (int)prev.region), (const uint32_t *)(smem + (b ? OFF_KEYS : OFF_KEYS2)));
-        }
         zero_lds(smem + OFF_M0, OFF_KEYS - OFF_M0);
         keys_clear(keys, R.ncx * R.ncy);
         Geo g0, g1, g2;
@@ -1530,6 +1531,15 @@ detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__
                         const fg_item ia = items[after];
                         region_prefetch(jobs[ia.job], (int)ia.region, T);
                     }
+                }
+                // the previous region's slots, written by the threads the
+                // tile commit leaves idle (quads past level-0 row 96); its
+                // keys buffer is next cleared after the next [A]
+                if (have_prev && threadIdx.x >= QUAD_THREADS) {
+                    const fg_job &Jp = jobs[prev.job];
+                    keys_write(Jp, region_of(Jp, (int)prev.region),
+                               (const uint32_t *)(smem + (b ? OFF_KEYS : OFF_KEYS2)), threadIdx.x - QUAD_THREADS,
+                               blockDim.x - QUAD_THREADS);
                 }
             });
         prev = il;
