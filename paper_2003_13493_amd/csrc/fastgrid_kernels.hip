@@ -1187,19 +1187,20 @@ static_assert(SUB + 2 * (4 << (MAX_FUSED - 1)) <= 96, "fused tiles have at most 
 //
 // The loads go through a buffer resource over the plane rows the tile covers
 // (H * P bytes of a plane are addressable): a row above or below the plane
-// reads zero through the buffer's range check, and a chunk left or right of
-// the plane reads bytes of a neighbouring row.  No pixel outside the plane is
-// ever used as a pixel value (it is never testable, never inside a testable
-// pixel's circle, and never written to a level plane), so the loads need no
-// other guard.  Chunks a thread does not load keep stale values, which
-// quad_commit never reads.
+// reads zero through the buffer's range check.  A chunk left or right of the
+// plane is not loaded and keeps stale register values.  No pixel outside the
+// plane is ever used as a pixel value (it is never testable, never inside a
+// testable pixel's circle, and never written to a level plane), so the tile
+// needs no zeros there.  Chunks a thread does not own keep stale values too,
+// which quad_commit never reads.
 __device__ __forceinline__ void quad_issue(TileRegs &R, const uint8_t *img, int H, int P, const Stage &st) {
     const int ch = threadIdx.x & 7, q = threadIdx.x >> 3;
-    if (ch >= (st.tw >> 4) || 4 * q >= st.th) return;
+    const int gx = st.tx + 16 * ch;
+    if (ch >= (st.tw >> 4) || 4 * q >= st.th || gx < 0 || gx >= P) return;
     const int y0 = max(st.ty, 0), y1 = min(st.ty + st.th, H);
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
         (void *)(img + (ptrdiff_t)y0 * P), (short)0, max(y1 - y0, 0) * P, 0x00020000);
-    int off = (st.ty + 4 * q - y0) * P + st.tx + 16 * ch;   // negative: out of range, reads zero
+    int off = (st.ty + 4 * q - y0) * P + gx;   // negative: out of range, reads zero
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         R.v[j] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
