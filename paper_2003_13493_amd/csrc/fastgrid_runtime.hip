@@ -120,6 +120,11 @@ struct fast_ctx {
     std::vector<Plan> plans;
     std::vector<Retired> retired;
     hipStream_t capture_stream = nullptr;
+    // the serving loops' launch streams, created on first use and kept for the
+    // context's life: the ticket events of their launches stay in the event
+    // ring after a loop returns, and an event must not outlive the stream it
+    // was last recorded on
+    hipStream_t pump_streams[FAST_PUMP_MAX_LANES] = {};
     // tuned region sides of one-frame calls, per frame shape (fast_set_shape_table)
     std::vector<fast_shape_region> shapes;
     // fast_submit_static: the device scratch address, a pinned staging buffer
@@ -482,6 +487,8 @@ FG_API void fast_ctx_destroy(fast_ctx *c) {
     for (auto &e : c->events)
         if (e) (void)hipEventDestroy(e);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    for (hipStream_t s : c->pump_streams)
+        if (s) (void)hipStreamDestroy(s);
     delete c;
 }
 
@@ -984,8 +991,11 @@ int pump_loop(fast_ctx *c, int nstreams, const std::vector<int> &nslots, const f
     for (int i = 0; i < nstreams; ++i) busy[i].assign(nslots[i], 0);
     int rc = FAST_OK;
     std::vector<PumpLane> lane(lanes);
-    for (PumpLane &L : lane) {
-        hipError_t e = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking);
+    for (int k = 0; k < lanes; ++k) {
+        PumpLane &L = lane[k];
+        hipError_t e = hipSuccess;
+        if (!c->pump_streams[k]) e = hipStreamCreateWithFlags(&c->pump_streams[k], hipStreamNonBlocking);
+        L.stream = c->pump_streams[k];
         if (e == hipSuccess) e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
         if (e != hipSuccess) {
             rc = hip_fail(c, e, "pump lane setup");
@@ -1065,10 +1075,9 @@ int pump_loop(fast_ctx *c, int nstreams, const std::vector<int> &nslots, const f
             ++nb;
         }
     }
-    for (PumpLane &L : lane) {
+    for (PumpLane &L : lane) {   // the streams stay with the context
         if (L.stream) (void)hipStreamSynchronize(L.stream);
         if (L.done) (void)hipEventDestroy(L.done);
-        if (L.stream) (void)hipStreamDestroy(L.stream);
     }
     *nbatches = nb;
     return rc;

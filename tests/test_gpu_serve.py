@@ -99,6 +99,30 @@ def test_native_loop_rejects_bad_arguments(ctx):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("batched", [True, False], ids=["batched", "plain"])
+def test_native_loop_runs_back_to_back(ctx, batched):
+    """Several serving-loop runs in a row, each with more launches than the
+    context tracks submissions (256), so every run recycles completion events
+    of the one before.  The loop's launch streams live as long as the
+    context, so each run succeeds and serves every frame."""
+    specs = small_streams()[:1]
+    srv = serve.Server(ctx, specs, pool_frames=1, slots_per_stream=1, max_batch=1, inflight=1)
+    st, spec = srv.streams[0], specs[0]
+    pool = (fastgrid.fast_plane * 1)(*st.pool_planes)
+    upper = (fastgrid.fast_plane * (spec.levels - 1))(*st.slots[0].planes[1:spec.levels])
+    import ctypes
+    out = (ctypes.c_void_p * 1)(st.slots[0].grid.data_ptr())
+    arr = (fastgrid.fast_pump_stream * 1)(fastgrid.fast_pump_stream(
+        spec.levels, spec.t, spec.n, spec.cell, 0, 1, pool, 1, upper, out, None))
+    n = 300
+    reqs = (fastgrid.fast_pump_request * n)(*[fastgrid.fast_pump_request(0, k, 0.0) for k in range(n)])
+    for run in range(3):
+        print(f"case native back-to-back batched={batched} run {run}", flush=True)
+        done, slot, nb = fastgrid.fast_pump_run(ctx.handle, arr, 1, reqs, n, 1, 1, batched, 30.0)
+        assert (done > 0).all() and nb == n
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("batched,upload", [(True, False), (False, False), (True, True)],
                          ids=["batched", "plain", "batched_upload"])
 def test_each_result_same_alone_and_in_mix(ctx, batched, upload):
