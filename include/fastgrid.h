@@ -35,6 +35,11 @@
  *     as void*, NULL for the null stream); results are valid after the stream
  *     synchronises or fast_poll reports completion.  Device faults surface as
  *     FAST_EHIP from a later call.
+ *   - A submission with a ticket leaves a completion event recorded on its
+ *     stream in the context's ring of 256; a later submission that reuses the
+ *     entry waits on that event unless fast_poll or fast_wait has already
+ *     reported the ticket complete.  Keep such a stream alive until then (the
+ *     serving loops' own streams live as long as the context).
  *   - All image planes and output arrays are device memory owned by the
  *     caller; the library never frees them.  The library owns only its context
  *     (job tables, queue counters, events, graphs, scratch).

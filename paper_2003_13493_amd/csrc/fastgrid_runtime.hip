@@ -309,7 +309,12 @@ int ticket_state(fast_ctx *c, uint64_t tk) {
     if (c->event_ticket[tk % TICKET_RING] != tk)
         return 1;   // its event was recycled, which only happens after it completed
     hipError_t e = hipEventQuery(c->events[tk % TICKET_RING]);
-    if (e == hipSuccess) return 1;
+    if (e == hipSuccess) {
+        // seen complete: the ring entry is free, so recycling it later needs
+        // no wait on an event whose stream may be gone by then
+        c->event_ticket[tk % TICKET_RING] = 0;
+        return 1;
+    }
     if (e == hipErrorNotReady) return 0;
     return hip_fail(c, e, "hipEventQuery");
 }
