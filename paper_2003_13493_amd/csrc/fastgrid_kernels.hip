@@ -1511,7 +1511,10 @@ detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__
         Geo g0, g1, g2;
         describe_fused(J, R.P.rx0, R.P.ry0, R.xr1, R.yr1, st, g0, g1, g2);
         __syncthreads();   // [B]
-        unsigned ticket = 0;
+        // thread 0 only, read only where it was set; left without a value
+        // elsewhere so that no copy of the atomic's result (which would wait
+        // for it at once) is needed where the branch rejoins
+        unsigned ticket;
         if (threadIdx.x == 0 && next < total) ticket = queue_ticket(q);
         int after = total;
         // the staged geometry depends only on the fused level count and the
