@@ -1515,7 +1515,9 @@ detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__
         // elsewhere so that no copy of the atomic's result (which would wait
         // for it at once) is needed where the branch rejoins
         unsigned ticket;
-        if (threadIdx.x == 0 && next < total) ticket = queue_ticket(q);
+        // (the first lane of the last wave: wave 0 already carries the extra
+        // compass round of a full region, so it sets the region's pace)
+        if (threadIdx.x == blockDim.x - 64 && next < total) ticket = queue_ticket(q);
         int after = total;
         // the staged geometry depends only on the fused level count and the
         // region's size once its origin is 16-aligned across and 4-aligned down
@@ -1525,7 +1527,8 @@ detect_batch_kernel(const fg_job *__restrict__ jobs, const fg_item *__restrict__
         run_passes(
             smem, g0, g1, g2, fused_levels(J), R.P, keys, &gcache, gkey,
             [&]() {
-                if (threadIdx.x == 0) s_next[b] = next < total ? queue_item(q, 2LL * q.n + ticket, total) : total;
+                if (threadIdx.x == blockDim.x - 64)
+                    s_next[b] = next < total ? queue_item(q, 2LL * q.n + ticket, total) : total;
             },
             [&]() {   // after [C]
                 after = __builtin_amdgcn_readfirstlane(s_next[b]);
